@@ -1,0 +1,74 @@
+"""The SMC loop of Alg. 1 with a pCN-GM mutation (SMC-pCN-GM).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Per stage, in the order of the operator form S^N P_{j+1} L_{j+1} (Sec. 2.2,
+eq. (decidemuJN)): re-weight with the next increment h (Alg. 1, App. C), resample
+(every stage, since Alg. 1 resets the weights to 1/N), fit the mixture to the
+resampled cloud, then n_moves pCN-GM steps (Alg. 2) at the new temperature, and
+finally the App. C step-size rule
+    beta <- 2 beta if mean acceptance > 0.3, beta / 2 if < 0.15, else unchanged,
+capped at beta <= 1 since the proposal needs beta in (0, 1] (Sec. 2.3).
+The loop stops when the cumulative temperature reaches 1 (sum_j h_j = 1).
+
+Random numbers: the prior draw uses counter 0; stage s uses counters
+s * 2^20 + m for its moves and draws its resampling uniform from block
+RESAMPLE_BLOCK at counter s * 2^20.
+"""
+import numpy as np
+
+from . import gmfit, philox
+from .moves import GM, gmpcn_moves, pcn_gm, prior_sample
+from .resample import systematic
+from .temper import temper
+
+RESAMPLE_BLOCK = 0x80000001
+STAGE_STRIDE = 1 << 20
+
+
+def resample_u53(seed, ctr):
+    c = np.array([RESAMPLE_BLOCK, 0, ctr & philox.MASK32, (ctr >> 32) & philox.MASK32], dtype=np.uint64)
+    w = philox.philox4x32_10(c, philox._key(seed))
+    return (int(w[0]) >> 5) * (1 << 26) + (int(w[1]) >> 6)
+
+
+def adapt_beta(beta, rate):
+    if rate > 0.3:
+        return min(1.0, 2.0 * beta)
+    if rate < 0.15:
+        return 0.5 * beta
+    return beta
+
+
+def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stages=500):
+    """Returns dict(xi, phi, taus, log_Z, betas, rates)."""
+    from .forward import phi as phi_pde
+    K = prob.K
+    f = phi_fn if phi_fn is not None else (lambda x: phi_pde(prob, x, n))
+    active = prob.active() if kr is None else np.arange(kr)
+    xi = prior_sample(K, N, seed, 0)
+    phi = np.array([f(x) for x in xi])
+    tau, beta, log_Z = 0.0, float(beta0), 0.0
+    taus, betas, rates = [0.0], [], []
+    for s in range(1, max_stages + 1):
+        h, tau, W, lz, stalled = temper(phi, tau, rho)
+        if stalled:
+            raise RuntimeError("temperature bisection stalled")
+        log_Z += lz
+        taus.append(tau)
+        idx = systematic(W, resample_u53(seed, s * STAGE_STRIDE))
+        xi, phi = xi[idx], phi[idx]
+        if M == 1:
+            gm = pcn_gm(K, active)
+        else:
+            logw, mean, var = gmfit.fit(xi[:, active], M, seed=seed + s)
+            gm = GM(logw, mean, var, active, K)
+        xi, phi, n_acc = gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
+                                     phi_fn=f)
+        rate = n_acc.sum() / (N * n_moves)
+        betas.append(beta)
+        rates.append(rate)
+        beta = adapt_beta(beta, rate)
+        if tau >= 1.0:
+            break
+    return dict(xi=xi, phi=phi, taus=np.array(taus), log_Z=log_Z, betas=betas, rates=rates)
