@@ -1,0 +1,181 @@
+/*
+ * smc.h — C ABI of the MI355X move stage of Gaussian-mixture sequential Monte Carlo
+ * (arXiv 2503.16028, "Sequential Monte Carlo with Gaussian Mixture Approximation for
+ * Infinite-Dimensional Statistical Inverse Problems").
+ *
+ * Conventions shared by every call
+ *  - Array arguments are DEVICE pointers owned by the caller, unless marked "host".
+ *    Arrays are row-major and particle-major: row n of an [N][K] array is particle n.
+ *  - A particle is the vector xi of K whitened Karhunen-Loeve coefficients of the
+ *    log-permeability u = sum_i sqrt(lambda_i) xi_i phi_i (prior mu_0 = N(0, C), Sec. 2.1;
+ *    C_0 = (I - Delta)^{-2}, Sec. 3.2).  2D: K = kl*kl, index k*kl + l for
+ *    phi_kl = c_k c_l cos(k pi x) cos(l pi y); 1D: K = kl, index k-1 for sqrt(2) sin(k pi x).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream),
+ *    validates all arguments on the host before launching anything, and returns an
+ *    smc_status.  On SMC_E_INVAL nothing was launched and no output was touched.
+ *    Errors reported by the HIP runtime surface as SMC_E_HIP at that call or a later one.
+ *    smc_last_error() gives a text for the last non-OK status of the calling thread.
+ *  - No call allocates device memory except smc_problem_create, which allocates all the
+ *    workspace the other calls need for up to n_max particles.  Calls on one problem
+ *    share that workspace: they must not run concurrently on different streams.
+ *  - Failures found on the device (a solve that does not converge, a stalled temperature
+ *    step, a non-finite potential) set bits in the problem's device status word, read by
+ *    smc_status_flags(), and are also visible per particle in the outputs.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMC_OK = 0,
+    SMC_E_INVAL = -1,     /* invalid argument: nothing launched */
+    SMC_E_HIP = -2,       /* HIP runtime error */
+    SMC_E_NOCONV = -3,    /* (flag) a forward solve did not converge */
+    SMC_E_STALL = -4,     /* (flag) temperature bisection found no positive step */
+    SMC_E_NONFINITE = -5, /* (flag) no particle had a finite potential */
+    SMC_E_NOMEM = -6      /* workspace allocation failed */
+} smc_status;
+
+/* Bits of the device status word. */
+#define SMC_FLAG_NOCONV 1
+#define SMC_FLAG_STALL 2
+#define SMC_FLAG_NONFINITE 4
+#define SMC_FLAG_BADWEIGHTS 8
+
+typedef enum {
+    SMC_FP64 = 0,        /* conjugate gradients in FP64 */
+    SMC_FP32_REFINE = 1  /* FP32 conjugate gradients inside FP64 residual refinement */
+} smc_precision;
+
+typedef void* smc_stream; /* hipStream_t */
+typedef struct smc_problem_s* smc_problem;
+
+/* Problem definition (host memory; copied by smc_problem_create).
+ * Forward map (Sec. 3.2, eq. (example2:PDE), gradient on the state):
+ *   -div(e^u grad w) = f on (0,1)^dim, w = 0 on the boundary, discretised in flux form on a
+ *   grid of n intervals per axis (h = 1/n, nodes i/n), face coefficient exp((u_P + u_Q)/2).
+ * Observation F(u) = (w(x_1), ..., w(x_Nd)) at grid nodes; potential (Sec. 2.1)
+ *   Phi = |F(u) - y|^2 / (2 sigma^2). */
+typedef struct {
+    int32_t dim;            /* 1 or 2 */
+    int32_t n_levels;       /* number of grids, 1..3 (several grids: mixed-resolution runs) */
+    int32_t grid_n[3];      /* intervals per axis of each grid: powers of two, 2D 16..256, 1D 8..1024 */
+    int32_t kl;             /* KL modes per axis: 2D kl*kl cosine modes, kl <= 32; 1D kl <= 64 */
+    int32_t kr;             /* modes the mixture moves (the kr largest eigenvalues), 1..64, <= K */
+    int32_t n_obs;          /* 1..64 observations */
+    int32_t obs_den;        /* observation coordinates are obs_num / obs_den */
+    const int32_t* obs_num; /* host [n_obs][dim]; each point must be a node of every grid */
+    const double* y;        /* host [n_obs] data */
+    double sigma;           /* noise standard deviation, > 0 */
+    double f;               /* constant source term */
+    int64_t n_max;          /* largest particle count any call will pass */
+    double tol64;           /* stop when ||f - A w||_2 <= tol64 ||f||_2 with the FP64 operator */
+    double tol_inner;       /* FP32 inner solves reduce their residual by this factor */
+    int32_t max_iter;       /* cap on conjugate-gradient iterations per solve (all sweeps) */
+    int32_t max_sweeps;     /* cap on FP64 refinement sweeps per solve */
+} smc_problem_desc;
+
+/* Mixture {w_j, m_j, C_j} of Sec. 2.3 (C_j shares the prior's eigenfunctions), in whitened
+ * coordinates over the kr active modes; all device pointers.
+ *   logw[M]        log mixture weights (normalised)
+ *   mean[M][kr]    whitened means  m~_ji = <m_j, phi_i> / sqrt(lambda_i)
+ *   scale[M][kr]   variance ratios s_ji = lambda_ji / lambda_i  (> 0)
+ * Outside the active modes every component has mean 0 and scale 1. */
+typedef struct {
+    int32_t M;            /* 1..16 */
+    int32_t kr;           /* must equal the problem's kr */
+    const double* logw;
+    const double* mean;
+    const double* scale;
+} smc_gm;
+
+/* Create a problem: copies the definition, tabulates the prior and the grids on the device,
+ * allocates all workspace for n_max particles.  *out is set only on SMC_OK. */
+int smc_problem_create(const smc_problem_desc* desc, smc_problem* out);
+/* Free a problem and its workspace (waits for the device).  NULL is ignored. */
+void smc_problem_destroy(smc_problem p);
+/* Text of the last non-OK status returned on the calling thread. */
+const char* smc_last_error(void);
+/* K, the active mode list (host out [kr]) and the observation count; any pointer may be NULL. */
+int smc_problem_info(smc_problem p, int32_t* K, int32_t* active, int32_t* n_obs);
+/* Synchronise `stream`, return the device status word in *flags (host) and clear it if
+ * `clear` is nonzero. */
+int smc_status_flags(smc_problem p, smc_stream stream, int32_t* flags, int32_t clear);
+
+/* Initial draw of Alg. 1: xi[N][K] ~ N(0, I) from Philox4x32-10 (Salmon et al., SC'11) with
+ * key = (seed lo, seed hi), counter = (i/2, particle, ctr lo, ctr hi) and Box-Muller. */
+int smc_prior_sample(smc_problem p, int64_t N, uint64_t seed, uint64_t ctr, double* xi,
+                     smc_stream stream);
+
+/* Nodal field u = sum_i sqrt(lambda_i) xi_i phi_i on grid `level`: u[N][n+1][n+1]
+ * (2D, index [j][i] for the node (i/n, j/n)) or u[N][n+1] (1D). */
+int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, double* u,
+                   smc_stream stream);
+
+/* Forward map G = F(u(xi)) for N particles (one PDE solve each, Sec. 3.2).
+ *   level  [N] grid index per particle, or NULL for grid 0
+ *   prec   smc_precision (1D problems always solve directly in FP64)
+ *   G      [N][n_obs] out; NaN rows for solves that did not converge
+ *   iters  [N] out, conjugate-gradient iterations, -1 when not converged; may be NULL */
+int smc_forward_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level,
+                      int32_t prec, double* G, int32_t* iters, smc_stream stream);
+
+/* Potential Phi = |G - y|^2 / (2 sigma^2) (Sec. 2.1): phi[N] out, +inf for non-finite rows. */
+int smc_potential(smc_problem p, int64_t N, const double* G, double* phi, smc_stream stream);
+
+/* n_moves steps of the pCN-GM kernel (Sec. 2.3, Alg. 2) targeting exp(-tau Phi) mu_0:
+ *   proposal  v = gamma xi + (1 - gamma) m_j + beta sqrt(s_j) z on the active modes and
+ *             v = gamma xi + beta z elsewhere, gamma = sqrt(1 - beta^2), component
+ *             j = min{j : w_1 + ... + w_j > U_comp}, z ~ N(0, I);
+ *   acceptance a = min{1, rho(dv) Q(v, dxi) / (rho(dxi) Q(xi, dv))} (eqs. (auv of pCN-GMM)),
+ *             accept iff log U_acc < log a.
+ * Move m draws from counter ctr + m: normals as in smc_prior_sample, (U_comp, U_acc) from
+ * block 0x80000000.  M = 1 with zero mean and unit scale is plain pCN.
+ *   xi [N][K], phi [N] in/out (phi must be the potential of xi); n_acc [N] out (accept count).
+ * A proposal whose solve does not converge gets Phi = +inf and is rejected. */
+int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
+                   int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level,
+                   int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
+
+/* Re-weighting and next temperature (Alg. 1; App. C): with tau = *tau_in (device scalar),
+ * choose h in (0, 1 - tau] by 64 bisection steps keeping ESS(h) >= ess_frac * N, where
+ * ESS = 1 / sum W^2 and W_n ∝ exp(-h Phi_n); take h = 1 - tau when that already passes.
+ * Outputs (device): *h, *tau_new (= 1 exactly on the last stage), W[N] normalised weights,
+ * *log_z_inc = log((1/N) sum exp(-h Phi)).  Non-finite Phi get weight 0.  A zero step sets
+ * SMC_FLAG_STALL and no finite potential sets SMC_FLAG_NONFINITE in *flags (device, may be
+ * NULL), which is or-ed, never cleared.  N <= 1048576. */
+int smc_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,
+               double* tau_new, double* W, double* log_z_inc, int32_t* flags, smc_stream stream);
+
+/* Systematic resampling (Alg. 1, resampling step) on an exact integer CDF:
+ *   q_n = floor(W_n 2^53), C_n = q_0 + ... + q_n, Q = C_{N-1},
+ *   idx_i = min{n : C_n > floor((i 2^53 + u53) Q / (N 2^53))},  i = 0..N-1.
+ * u53 in [0, 2^53) is the uniform times 2^53.  idx[N] out (nondecreasing).  All-zero weights
+ * set SMC_FLAG_BADWEIGHTS in *flags (device, may be NULL) and give idx = 0..N-1.  N <= 16384. */
+int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags,
+                 smc_stream stream);
+
+/* Row gather after resampling: xi_out[i] = xi_in[idx[i]], phi_out[i] = phi_in[idx[i]]
+ * (phi pointers may be NULL).  Outputs must not alias inputs. */
+int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
+               const double* phi_in, double* xi_out, double* phi_out, smc_stream stream);
+
+/* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by
+ * smc_forward_batch and smc_gmpcn_move on p is then bracketed by two HIP events recorded on
+ * the call's stream, and the solve kernels add their conjugate-gradient iterations, FP64
+ * residual sweeps and solve count to a device counter.  smc_profile(p, 0) stops.
+ * smc_profile_read synchronises `stream` and returns the summed kernel time (ms), the number
+ * of timed launches, and the iteration, sweep and solve totals (host outputs, any may be NULL). */
+int smc_profile(smc_problem p, int32_t enable);
+int smc_profile_read(smc_problem p, smc_stream stream, double* ms, int64_t* launches, int64_t* iters,
+                     int64_t* sweeps, int64_t* solves);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMC_H */

@@ -105,16 +105,17 @@ def propose_gmpcn(gm, beta, xi, z, u_comp):
     return gamma * xi + (1.0 - gamma) * m[j] + beta * np.sqrt(s[j]) * z, j
 
 
-def gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, ctr, phi_fn=None):
+def gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, ctr, phi_fn=None, ids=None):
     """n_moves pCN-GM steps (Alg. 2) for every particle; returns (xi, phi, n_acc).
 
-    Random numbers follow the layout in `philox`; particle ids are row numbers.
-    phi_fn(xi) -> Phi overrides the PDE potential (used by tests with closed forms).
+    Random numbers follow the layout in `philox`; particle ids are row numbers unless
+    `ids` gives them.  phi_fn(xi) -> Phi overrides the PDE potential (used by tests with
+    closed forms).
     """
     xi = np.array(xi, dtype=np.float64, copy=True)
     phi = np.array(phi, dtype=np.float64, copy=True)
     N, K = xi.shape
-    ids = np.arange(N)
+    ids = np.arange(N) if ids is None else np.asarray(ids)
     n_acc = np.zeros(N, dtype=np.int64)
     f = phi_fn if phi_fn is not None else (lambda x: phi_of(prob, x, n))
     for mv in range(n_moves):

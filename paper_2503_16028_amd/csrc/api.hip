@@ -1,0 +1,422 @@
+// C ABI of libsmc: argument validation, device tables, workspace and the launch sequence of
+// each call.  Every argument is checked before anything is launched.
+#include <stdarg.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace smc;
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;   // pairs: ev[2k] before, ev[2k+1] after launch k
+    size_t used = 0;              // events recorded since the last read
+};
+
+struct smc_problem_s {
+    Problem P;
+    int device = 0;
+    EventPool pool;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(SMC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+template <typename T>
+static hipError_t upload(T** dst, const T* src, size_t n) {
+    hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static void free_problem(Problem& P) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    for (int l = 0; l < MAX_LEVELS; ++l) { f(P.lv[l].basis); f(P.lv[l].obs_node); }
+    f(P.sqrt_lam); f(P.active); f(P.slot); f(P.y);
+    f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_sd); f(P.ws_vec);
+    f(P.ws_G); f(P.ws_iters); f(P.flags); f(P.stats);
+}
+
+extern "C" const char* smc_last_error(void) { return g_err.c_str(); }
+
+extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
+    if (!d || !out) return fail(SMC_E_INVAL, "desc and out must not be NULL");
+    if (d->dim != 1 && d->dim != 2) return fail(SMC_E_INVAL, "dim must be 1 or 2 (got %d)", d->dim);
+    if (d->n_levels < 1 || d->n_levels > MAX_LEVELS) return fail(SMC_E_INVAL, "n_levels must be 1..3");
+    for (int l = 0; l < d->n_levels; ++l) {
+        const bool okn = d->dim == 2 ? pow2_in(d->grid_n[l], 16, 256) : pow2_in(d->grid_n[l], 8, 1024);
+        if (!okn) return fail(SMC_E_INVAL, "grid_n[%d] = %d is not a supported power of two", l, d->grid_n[l]);
+    }
+    if (d->dim == 2 && (d->kl < 1 || d->kl > 32)) return fail(SMC_E_INVAL, "2D kl must be 1..32");
+    if (d->dim == 1 && (d->kl < 1 || d->kl > 64)) return fail(SMC_E_INVAL, "1D kl must be 1..64");
+    const int K = d->dim == 2 ? d->kl * d->kl : d->kl;
+    if (d->kr < 1 || d->kr > MAX_KR || d->kr > K) return fail(SMC_E_INVAL, "kr must be 1..min(64, K)");
+    if (d->n_obs < 1 || d->n_obs > MAX_OBS) return fail(SMC_E_INVAL, "n_obs must be 1..64");
+    if (d->obs_den < 1 || !d->obs_num || !d->y) return fail(SMC_E_INVAL, "observation arrays missing");
+    if (!(d->sigma > 0.0) || !std::isfinite(d->sigma)) return fail(SMC_E_INVAL, "sigma must be positive");
+    if (!std::isfinite(d->f)) return fail(SMC_E_INVAL, "f must be finite");
+    if (d->n_max < 1 || d->n_max > (1 << 24)) return fail(SMC_E_INVAL, "n_max must be 1..2^24");
+    if (!(d->tol64 > 0.0) || !(d->tol_inner > 0.0 && d->tol_inner < 1.0))
+        return fail(SMC_E_INVAL, "tolerances must be positive (tol_inner < 1)");
+    if (d->max_iter < 1 || d->max_sweeps < 1) return fail(SMC_E_INVAL, "max_iter and max_sweeps must be >= 1");
+    for (int k = 0; k < d->n_obs; ++k) {
+        if (!std::isfinite(d->y[k])) return fail(SMC_E_INVAL, "y[%d] is not finite", k);
+        for (int a = 0; a < d->dim; ++a) {
+            const int num = d->obs_num[k * d->dim + a];
+            if (num <= 0 || num >= d->obs_den) return fail(SMC_E_INVAL, "observation %d is not interior", k);
+            for (int l = 0; l < d->n_levels; ++l)
+                if (((int64_t)num * d->grid_n[l]) % d->obs_den)
+                    return fail(SMC_E_INVAL, "observation %d is not a node of grid %d", k, d->grid_n[l]);
+        }
+    }
+
+    smc_problem_s* ps = new smc_problem_s();
+    Problem& P = ps->P;
+    (void)hipGetDevice(&ps->device);
+    P.dim = d->dim;
+    P.n_levels = d->n_levels;
+    P.kl = d->kl;
+    P.K = K;
+    P.kr = d->kr;
+    P.n_obs = d->n_obs;
+    P.sigma = d->sigma;
+    P.f = d->f;
+    P.tol64 = d->tol64;
+    P.tol_inner = d->tol_inner;
+    P.max_iter = d->max_iter;
+    P.max_sweeps = d->max_sweeps;
+    P.n_max = d->n_max;
+
+    // prior: sqrt(lambda) and the active modes (largest lambda first, ties to the lower index)
+    std::vector<double> sl(K);
+    std::vector<int> key(K);
+    for (int idx = 0; idx < K; ++idx) {
+        double mu;
+        if (P.dim == 2) {
+            const int k = idx / P.kl, l = idx % P.kl;
+            key[idx] = k * k + l * l;
+            mu = 1.0 + M_PI * M_PI * (double)(k * k + l * l);
+        } else {
+            key[idx] = idx;
+            mu = 1.0 + M_PI * M_PI * (double)((idx + 1) * (idx + 1));
+        }
+        sl[idx] = 1.0 / mu;   // sqrt of lambda = mu^{-2}
+    }
+    std::vector<int> order(K);
+    for (int idx = 0; idx < K; ++idx) order[idx] = idx;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int32_t> act(order.begin(), order.begin() + P.kr), slot(K, -1);
+    for (int a = 0; a < P.kr; ++a) {
+        slot[act[a]] = a;
+        P.active_h[a] = act[a];
+    }
+
+    hipError_t e = hipSuccess;
+    auto ck = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    ck(upload(&P.sqrt_lam, sl.data(), K));
+    ck(upload(&P.active, act.data(), act.size()));
+    ck(upload(&P.slot, slot.data(), slot.size()));
+    ck(upload(&P.y, d->y, P.n_obs));
+    P.n_big = 0;
+    for (int l = 0; l < P.n_levels; ++l) {
+        const int n = d->grid_n[l];
+        P.lv[l].n = n;
+        P.n_big = std::max(P.n_big, n);
+        std::vector<double> B;
+        if (P.dim == 2) {
+            B.assign((size_t)(n + 1) * KLP, 0.0);
+            for (int i = 0; i <= n; ++i)
+                for (int k = 0; k < P.kl; ++k)
+                    B[(size_t)i * KLP + k] = (k == 0 ? 1.0 : std::sqrt(2.0)) * std::cos(M_PI * k * (double)i / n);
+        } else {
+            B.assign((size_t)(n + 1) * P.kl, 0.0);
+            for (int i = 0; i <= n; ++i)
+                for (int k = 0; k < P.kl; ++k)
+                    B[(size_t)i * P.kl + k] = std::sqrt(2.0) * std::sin(M_PI * (k + 1) * (double)i / n);
+        }
+        ck(upload(&P.lv[l].basis, B.data(), B.size()));
+        std::vector<int32_t> nodes(P.n_obs);
+        for (int k = 0; k < P.n_obs; ++k) {
+            const int ii = (int)((int64_t)d->obs_num[k * P.dim] * n / d->obs_den);
+            if (P.dim == 2) {
+                const int jj = (int)((int64_t)d->obs_num[k * P.dim + 1] * n / d->obs_den);
+                nodes[k] = jj * (n + 1) + ii;
+            } else {
+                nodes[k] = ii;
+            }
+        }
+        ck(upload(&P.lv[l].obs_node, nodes.data(), nodes.size()));
+    }
+    const int64_t nb = P.n_big;
+    P.e_stride = P.dim == 2 ? (nb + 1) * (nb + 1) : nb + 1;
+    P.x_stride = P.e_stride;
+    P.vec_stride = P.dim == 2 ? 6 * nb * nb : 0;
+    const int64_t Nm = P.n_max;
+    ck(hipMalloc((void**)&P.ws_v, sizeof(double) * Nm * K));
+    ck(hipMalloc((void**)&P.ws_logr, sizeof(double) * Nm));
+    ck(hipMalloc((void**)&P.ws_phinew, sizeof(double) * Nm));
+    ck(hipMalloc((void**)&P.ws_e, sizeof(double) * Nm * P.e_stride));
+    ck(hipMalloc((void**)&P.ws_x64, sizeof(double) * Nm * P.x_stride));
+    ck(hipMalloc((void**)&P.ws_sd, sizeof(double) * Nm * P.x_stride));
+    if (P.dim == 2 && P.n_big >= 128) ck(hipMalloc(&P.ws_vec, sizeof(double) * Nm * P.vec_stride));
+    ck(hipMalloc((void**)&P.ws_G, sizeof(double) * Nm * P.n_obs));
+    ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
+    ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
+    ck(hipMalloc((void**)&P.stats, 3 * sizeof(unsigned long long)));
+    ck(hipMemset(P.stats, 0, 3 * sizeof(unsigned long long)));
+    ck(hipMemset(P.flags, 0, sizeof(int32_t)));
+    ck(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        free_problem(P);
+        delete ps;
+        return fail(e == hipErrorOutOfMemory ? SMC_E_NOMEM : SMC_E_HIP, "problem setup: %s", hipGetErrorString(e));
+    }
+    *out = ps;
+    return SMC_OK;
+}
+
+extern "C" void smc_problem_destroy(smc_problem p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->pool.ev) (void)hipEventDestroy(e);
+    free_problem(p->P);
+    delete p;
+}
+
+// Record one event of the current solve launch's bracket on stream s.
+static hipError_t record(EventPool& pool, hipStream_t s) {
+    if (pool.used == pool.ev.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        pool.ev.push_back(e);
+    }
+    return hipEventRecord(pool.ev[pool.used++], s);
+}
+
+extern "C" int smc_profile(smc_problem p, int32_t enable) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (enable) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemset(p->P.stats, 0, 3 * sizeof(unsigned long long)));
+        HIPCHK(hipDeviceSynchronize());
+        p->pool.used = 0;
+    }
+    p->P.profiling = enable != 0;
+    return SMC_OK;
+}
+
+extern "C" int smc_profile_read(smc_problem p, smc_stream stream, double* ms, int64_t* launches, int64_t* iters,
+                                int64_t* sweeps, int64_t* solves) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < p->pool.used; k += 2) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, p->pool.ev[k], p->pool.ev[k + 1]));
+        tot += t;
+    }
+    unsigned long long st[3];
+    HIPCHK(hipMemcpy(st, p->P.stats, sizeof(st), hipMemcpyDeviceToHost));
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)(p->pool.used / 2);
+    if (iters) *iters = (int64_t)st[0];
+    if (sweeps) *sweeps = (int64_t)st[1];
+    if (solves) *solves = (int64_t)st[2];
+    return SMC_OK;
+}
+
+extern "C" int smc_problem_info(smc_problem p, int32_t* K, int32_t* active, int32_t* n_obs) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (K) *K = p->P.K;
+    if (n_obs) *n_obs = p->P.n_obs;
+    if (active) std::copy(p->P.active_h, p->P.active_h + p->P.kr, active);
+    return SMC_OK;
+}
+
+extern "C" int smc_status_flags(smc_problem p, smc_stream stream, int32_t* flags, int32_t clear) {
+    if (!p || !flags) return fail(SMC_E_INVAL, "problem and flags must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(flags, p->P.flags, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (clear) {
+        HIPCHK(launch_fill_i32(p->P.flags, 1, 0, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return SMC_OK;
+}
+
+static int check_n(const Problem& P, int64_t N) {
+    if (N < 0 || N > P.n_max) return fail(SMC_E_INVAL, "N = %lld outside 0..n_max (%lld)", (long long)N,
+                                          (long long)P.n_max);
+    return SMC_OK;
+}
+
+extern "C" int smc_prior_sample(smc_problem p, int64_t N, uint64_t seed, uint64_t ctr, double* xi,
+                                smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int r = check_n(p->P, N)) return r;
+    if (N > 0 && !xi) return fail(SMC_E_INVAL, "xi is NULL");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    HIPCHK(launch_prior(N, p->P.K, seed, ctr, xi, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+// exp(u/2) (or u) of the particles' fields on one grid into `out`.
+static hipError_t synth(const Problem& P, int level, int64_t N, const double* xi, double* out, int64_t stride,
+                        bool exp_half, hipStream_t s) {
+    const Level& L = P.lv[level];
+    if (P.dim == 2) return launch_synth2d(xi, P.K, P.kl, P.sqrt_lam, L.basis, L.n, out, stride, N, exp_half, s);
+    return launch_synth1d(xi, P.kl, P.sqrt_lam, L.basis, L.n, out, stride, N, exp_half, s);
+}
+
+extern "C" int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, double* u,
+                              smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int r = check_n(p->P, N)) return r;
+    if (level < 0 || level >= p->P.n_levels) return fail(SMC_E_INVAL, "level %d out of range", level);
+    if (N > 0 && (!xi || !u)) return fail(SMC_E_INVAL, "xi and u must not be NULL");
+    const int n = p->P.lv[level].n;
+    const int64_t stride = p->P.dim == 2 ? (int64_t)(n + 1) * (n + 1) : n + 1;
+    HIPCHK(synth(p->P, level, N, xi, u, stride, false, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+static SolveArgs solve_args(const Problem& P, int level) {
+    SolveArgs a{};
+    a.e = P.ws_e;
+    a.x64 = P.ws_x64;
+    a.sd = P.ws_sd;
+    a.vec = P.ws_vec;
+    a.e_stride = P.e_stride;
+    a.x_stride = P.x_stride;
+    a.vec_stride = P.vec_stride;
+    a.row0 = 0;
+    a.obs = P.lv[level].obs_node;
+    a.n_obs = P.n_obs;
+    a.y = P.y;
+    a.inv2s2 = 0.5 / (P.sigma * P.sigma);
+    a.f = P.f;
+    a.tol64 = P.tol64;
+    a.tol_inner = P.tol_inner;
+    a.max_iter = P.max_iter;
+    a.max_sweeps = P.max_sweeps;
+    a.flags = P.flags;
+    a.stats = nullptr;
+    return a;
+}
+
+// Synthesis then solve for N particles of one grid; outputs per particle (any may be NULL).
+static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, double* G,
+                          double* phi, int32_t* iters, hipStream_t s) {
+    const Problem& P = ps->P;
+    hipError_t e = synth(P, level, N, xi, P.ws_e, P.e_stride, true, s);
+    if (e != hipSuccess) return e;
+    SolveArgs a = solve_args(P, level);
+    a.G = G;
+    a.phi = phi;
+    a.iters = iters;
+    a.stats = P.profiling ? P.stats : nullptr;
+    if (P.profiling && (e = record(ps->pool, s)) != hipSuccess) return e;
+    e = (P.dim == 2) ? launch_solve2d(P.lv[level].n, prec, N, a, s) : launch_solve1d(P.lv[level].n, N, a, s);
+    if (e != hipSuccess) return e;
+    if (P.profiling) e = record(ps->pool, s);
+    return e;
+}
+
+extern "C" int smc_forward_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level,
+                                 int32_t prec, double* G, int32_t* iters, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int r = check_n(p->P, N)) return r;
+    if (N > 0 && (!xi || !G)) return fail(SMC_E_INVAL, "xi and G must not be NULL");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (level) return fail(SMC_E_INVAL, "per-particle level maps are not supported by this call; pass NULL");
+    HIPCHK(forward(p, 0, prec, N, xi, G, nullptr, iters, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_potential(smc_problem p, int64_t N, const double* G, double* phi, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int r = check_n(p->P, N)) return r;
+    if (N > 0 && (!G || !phi)) return fail(SMC_E_INVAL, "G and phi must not be NULL");
+    HIPCHK(launch_potential(N, p->P.n_obs, G, p->P.y, 0.5 / (p->P.sigma * p->P.sigma), phi, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
+                              int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level, int32_t prec,
+                              double* xi, double* phi, int32_t* n_acc, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (int r = check_n(P, N)) return r;
+    if (!gm) return fail(SMC_E_INVAL, "gm is NULL");
+    if (gm->M < 1 || gm->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (gm->kr != P.kr) return fail(SMC_E_INVAL, "gm.kr (%d) differs from the problem's kr (%d)", gm->kr, P.kr);
+    if (!gm->logw || !gm->mean || !gm->scale) return fail(SMC_E_INVAL, "mixture arrays must not be NULL");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SMC_E_INVAL, "beta must be in (0, 1]");
+    if (!(tau >= 0.0 && tau <= 1.0)) return fail(SMC_E_INVAL, "tau must be in [0, 1]");
+    if (n_moves < 0) return fail(SMC_E_INVAL, "n_moves must be >= 0");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (level) return fail(SMC_E_INVAL, "per-particle level maps are not supported by this call; pass NULL");
+    if (N > 0 && (!xi || !phi || !n_acc)) return fail(SMC_E_INVAL, "xi, phi and n_acc must not be NULL");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_fill_i32(n_acc, N, 0, s));
+    for (int m = 0; m < n_moves; ++m) {
+        const uint64_t c = ctr + (uint64_t)m;
+        HIPCHK(launch_propose(N, P.K, P.kr, gm->M, P.active, P.slot, gm->logw, gm->mean, gm->scale, beta, seed, c,
+                              xi, P.ws_v, P.ws_logr, s));
+        HIPCHK(forward(p, 0, prec, N, P.ws_v, nullptr, P.ws_phinew, P.ws_iters, s));
+        HIPCHK(launch_accept(N, P.K, tau, seed, c, P.ws_v, P.ws_logr, P.ws_phinew, xi, phi, n_acc, s));
+    }
+    return SMC_OK;
+}
+
+extern "C" int smc_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,
+                          double* tau_new, double* W, double* log_z_inc, int32_t* flags, smc_stream stream) {
+    if (N < 1 || N > (1 << 20)) return fail(SMC_E_INVAL, "N must be 1..2^20");
+    if (!phi || !tau_in || !h || !tau_new || !W || !log_z_inc)
+        return fail(SMC_E_INVAL, "temper arrays must not be NULL");
+    if (!(ess_frac > 0.0 && ess_frac < 1.0)) return fail(SMC_E_INVAL, "ess_frac must be in (0, 1)");
+    HIPCHK(launch_temper(N, phi, tau_in, ess_frac, h, tau_new, W, log_z_inc, flags, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags,
+                            smc_stream stream) {
+    if (N < 1 || N > 16384) return fail(SMC_E_INVAL, "N must be 1..16384");
+    if (!W || !idx) return fail(SMC_E_INVAL, "W and idx must not be NULL");
+    if (u53 >= (1ull << 53)) return fail(SMC_E_INVAL, "u53 must be below 2^53");
+    HIPCHK(launch_resample(N, W, u53, idx, flags, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in, const double* phi_in,
+                          double* xi_out, double* phi_out, smc_stream stream) {
+    if (N < 0 || K < 1) return fail(SMC_E_INVAL, "N must be >= 0 and K >= 1");
+    if (N > 0 && (!idx || !xi_in || !xi_out)) return fail(SMC_E_INVAL, "idx, xi_in and xi_out must not be NULL");
+    if (xi_in == xi_out || (phi_in && phi_in == phi_out)) return fail(SMC_E_INVAL, "outputs must not alias inputs");
+    HIPCHK(launch_gather(N, K, idx, xi_in, phi_in, xi_out, phi_out, (hipStream_t)stream));
+    return SMC_OK;
+}

@@ -1,0 +1,157 @@
+// Internal definitions shared by the kernels and the C ABI of libsmc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/smc.h"
+
+namespace smc {
+
+constexpr int MAX_LEVELS = 3;
+constexpr int MAX_OBS = 64;
+constexpr int MAX_M = 16;
+constexpr int MAX_KR = 64;
+constexpr int KLP = 32;          // 2D modes per axis, padded, in the synthesis tiles
+constexpr uint32_t UNIFORM_BLOCK = 0x80000000u;
+
+struct Level {
+    int n = 0;                   // intervals per axis
+    double* basis = nullptr;     // 2D: [(n+1)][KLP] c_k cos(k pi i / n); 1D: [(n+1)][kl] sqrt2 sin(k pi i / n)
+    int32_t* obs_node = nullptr; // [n_obs] flat nodal index (2D j*(n+1)+i, 1D i)
+};
+
+struct Problem {
+    int dim = 0, n_levels = 0, kl = 0, K = 0, kr = 0, n_obs = 0;
+    Level lv[MAX_LEVELS];
+    int n_big = 0;               // largest grid
+    double sigma = 1, f = 1, tol64 = 1e-10, tol_inner = 1e-5;
+    int max_iter = 0, max_sweeps = 0;
+    int64_t n_max = 0;
+    double* sqrt_lam = nullptr;  // [K]
+    int32_t* active = nullptr;   // [kr] active mode ids
+    int32_t* slot = nullptr;     // [K] position in the active list or -1
+    int32_t active_h[MAX_KR];
+    double* y = nullptr;         // [n_obs]
+    // workspace, all for n_max particles
+    double* ws_v = nullptr;      // [n_max][K]    proposals
+    double* ws_logr = nullptr;   // [n_max]       log R of the proposal
+    double* ws_phinew = nullptr; // [n_max]       potential of the proposal
+    double* ws_e = nullptr;      // [n_max][(n_big+1)^dim]  exp(u/2) at the nodes
+    double* ws_x64 = nullptr;    // [n_max][n_big^dim]      FP64 solution
+    double* ws_sd = nullptr;     // [n_max][n_big^2]        D^{-1/2} of the Jacobi scaling
+    void* ws_vec = nullptr;      // [n_max][6][n_big^2] doubles: vectors of the global-memory solver
+    double* ws_G = nullptr;      // [n_max][n_obs]
+    int32_t* ws_iters = nullptr; // [n_max]
+    int32_t* flags = nullptr;    // device status word
+    unsigned long long* stats = nullptr;  // [3] iterations, sweeps, solves (while profiling)
+    bool profiling = false;
+    void* events = nullptr;      // host-side event list (api.hip)
+    int64_t e_stride = 0, x_stride = 0, vec_stride = 0;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11):
+// ten rounds of two 32x32->64 products; the key is bumped by two Weyl constants
+// between rounds.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// 53-bit uniform in [0, 1) from two words.
+__device__ __forceinline__ double res53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * 0x1p-53;
+}
+
+// Two standard normals by Box-Muller from the four words of one block.
+__device__ __forceinline__ void box_muller(uint4 w, double& z0, double& z1) {
+    const double u1 = res53(w.x, w.y), u2 = res53(w.z, w.w);
+    const double rad = sqrt(-2.0 * log(1.0 - u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+
+__device__ __forceinline__ uint4 draw(uint64_t seed, uint64_t ctr, uint32_t block, uint32_t particle) {
+    return philox(make_uint4(block, particle, (uint32_t)ctr, (uint32_t)(ctr >> 32)), (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;   // identical in every lane (each butterfly step adds the same two operands)
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over the block in a fixed order; every thread gets the same bits.
+// `red` holds at least NW doubles of LDS; contains a barrier.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w];
+    return s;
+}
+
+// ------------------------------------------------------------------ launchers (defined in k_*.hip)
+struct SolveArgs {
+    const double* e;     // exp(u/2) nodal, row stride e_stride
+    double* x64;         // FP64 solution, row stride x_stride
+    double* sd;          // D^{-1/2}, row stride x_stride
+    void* vec;           // global-solver vectors, row stride vec_stride (doubles)
+    int64_t e_stride, x_stride, vec_stride;
+    int64_t row0;        // first particle row
+    const int32_t* obs;  // [n_obs] nodal flat index
+    int n_obs;
+    const double* y;
+    double inv2s2;       // 1 / (2 sigma^2)
+    double f, tol64, tol_inner;
+    int max_iter, max_sweeps;
+    double* G;           // [N][n_obs] or null
+    double* phi;         // [N] or null
+    int32_t* iters;      // [N] or null
+    int32_t* flags;
+    unsigned long long* stats;   // [3] iterations, sweeps, solves; null when not profiling
+};
+
+hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_lam, const double* basis, int n,
+                          double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
+hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, const double* basis, int n, double* out,
+                          int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
+hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStream_t s);
+hipError_t launch_solve1d(int n, int64_t N, const SolveArgs& a, hipStream_t s);
+
+hipError_t launch_prior(int64_t N, int K, uint64_t seed, uint64_t ctr, double* xi, hipStream_t s);
+hipError_t launch_potential(int64_t N, int n_obs, const double* G, const double* y, double inv2s2, double* phi,
+                            hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_propose(int64_t N, int K, int kr, int M, const int32_t* active, const int32_t* slot,
+                          const double* logw, const double* mean, const double* scale, double beta,
+                          uint64_t seed, uint64_t ctr, const double* xi, double* v, double* logr, hipStream_t s);
+hipError_t launch_accept(int64_t N, int K, double tau, uint64_t seed, uint64_t ctr, const double* v,
+                         const double* logr, const double* phinew, double* xi, double* phi, int32_t* n_acc,
+                         hipStream_t s);
+hipError_t launch_gather(int64_t N, int K, const int32_t* idx, const double* xi_in, const double* phi_in,
+                         double* xi_out, double* phi_out, hipStream_t s);
+hipError_t launch_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,
+                         double* tau_new, double* W, double* log_z, int32_t* flags, hipStream_t s);
+hipError_t launch_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,217 @@
+// Particle-level kernels of the move stage: prior draw, potential, pCN-GM proposal with its
+// acceptance ratio, Metropolis accept/reject and the row gather after resampling.
+#include "common.hpp"
+
+namespace smc {
+
+// xi[N][K] ~ N(0, I): normal i of particle n is element i % 2 of block i / 2.
+__global__ __launch_bounds__(256) void prior_kernel(int64_t N, int K, uint64_t seed, uint64_t ctr,
+                                                    double* __restrict__ xi) {
+    const int nb = (K + 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= N * nb) return;
+    const int64_t n = t / nb;
+    const int blk = (int)(t % nb);
+    double z0, z1;
+    box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z0, z1);
+    xi[n * K + 2 * blk] = z0;
+    if (2 * blk + 1 < K) xi[n * K + 2 * blk + 1] = z1;
+}
+
+hipError_t launch_prior(int64_t N, int K, uint64_t seed, uint64_t ctr, double* xi, hipStream_t s) {
+    const int64_t work = N * ((K + 1) / 2);
+    if (work <= 0) return hipSuccess;
+    prior_kernel<<<dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s>>>(N, K, seed, ctr, xi);
+    return hipGetLastError();
+}
+
+// Phi = |G - y|^2 / (2 sigma^2), +inf for a non-finite row (Sec. 2.1).
+__global__ __launch_bounds__(256) void potential_kernel(int64_t N, int n_obs, const double* __restrict__ G,
+                                                        const double* __restrict__ y, double inv2s2,
+                                                        double* __restrict__ phi) {
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    double s = 0.0;
+    bool fin = true;
+    for (int k = 0; k < n_obs; ++k) {
+        const double g = G[n * n_obs + k];
+        fin = fin && isfinite(g);
+        s += (g - y[k]) * (g - y[k]);
+    }
+    phi[n] = fin ? s * inv2s2 : INFINITY;
+}
+
+hipError_t launch_potential(int64_t N, int n_obs, const double* G, const double* y, double inv2s2, double* phi,
+                            hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    potential_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(N, n_obs, G, y, inv2s2, phi);
+    return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    fill_i32_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+// pCN-GM proposal (Sec. 2.3, eq. (pCN-GM proposal), component-wise) and its log ratio.
+//
+// The Metropolis-Hastings ratio rho(dv) Q(v, dxi) / (rho(dxi) Q(xi, dv)) of eq. (auv of
+// pCN-GMM) factors into exp(tau (Phi(xi) - Phi(v))) times the ratio R of the two mixture
+// joint measures mu_0(dv)Q(v, dxi) / mu_0(dxi)Q(xi, dv) (eq. (auv of pCN-GMM2)).  In whitened
+// coordinates the off-mixture modes contribute the symmetric pCN factor, which cancels, and
+// subtracting the same symmetric pCN term inside every component leaves
+//   log R = LSE_j[log w_j + alpha_j(xi, v)] - LSE_j[log w_j + alpha_j(v, xi)],
+//   alpha_j(a, b) = sum_{i active} (a_i - g b_i)^2 / (2 beta^2)
+//                   - (a_i - g b_i - (1 - g) m_ji)^2 / (2 beta^2 s_ji) - log(s_ji) / 2,
+// a sum over the active modes only (g = gamma).  The first argument of alpha is where the
+// reverse move lands.  This is the ratio of the Gaussian components' Radon-Nikodym
+// derivatives of eq. (auv of pCN-GMM4) written out for diagonal covariances.
+__global__ __launch_bounds__(256) void propose_kernel(int K, int kr, int M, const int32_t* __restrict__ active,
+                                                      const int32_t* __restrict__ slot,
+                                                      const double* __restrict__ logw,
+                                                      const double* __restrict__ mean,
+                                                      const double* __restrict__ scale, double beta,
+                                                      uint64_t seed, uint64_t ctr, const double* __restrict__ xi,
+                                                      double* __restrict__ v, double* __restrict__ logr) {
+    __shared__ int comp;
+    __shared__ double fw[MAX_M], bw[MAX_M];
+    const int64_t n = blockIdx.x;
+    const double gamma = sqrt(1.0 - beta * beta);
+    if (threadIdx.x == 0) {
+        const uint4 w = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const double uc = res53(w.x, w.y);
+        double cum = 0.0;
+        int j = M - 1;
+        for (int m = 0; m < M; ++m) {
+            cum += exp(logw[m]);
+            if (cum > uc) { j = m; break; }
+        }
+        comp = j;
+    }
+    __syncthreads();
+    const int j = comp;
+    const double* xp = xi + n * K;
+    double* vp = v + n * K;
+    const int nb = (K + 1) / 2;
+    for (int blk = threadIdx.x; blk < nb; blk += 256) {
+        double z[2];
+        box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * blk + h;
+            if (k >= K) break;
+            const int sl = slot[k];
+            double val = gamma * xp[k] + beta * z[h];
+            if (sl >= 0) {
+                const double m = mean[j * kr + sl], s = scale[j * kr + sl];
+                val = gamma * xp[k] + (1.0 - gamma) * m + beta * sqrt(s) * z[h];
+            }
+            vp[k] = val;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const double inv2b2 = 0.5 / (beta * beta);
+        double a_x = 0.0, a_v = 0.0;
+        if (lane < kr) {
+            const int k = active[lane];
+            a_x = xp[k];
+            a_v = vp[k];
+        }
+        for (int m = 0; m < M; ++m) {
+            double tf = 0.0, tb = 0.0;
+            if (lane < kr) {
+                const double mm = (1.0 - gamma) * mean[m * kr + lane], s = scale[m * kr + lane];
+                const double d1 = a_x - gamma * a_v, d2 = a_v - gamma * a_x;   // reverse, forward
+                tf = d1 * d1 * inv2b2 - (d1 - mm) * (d1 - mm) * inv2b2 / s - 0.5 * log(s);
+                tb = d2 * d2 * inv2b2 - (d2 - mm) * (d2 - mm) * inv2b2 / s - 0.5 * log(s);
+            }
+            tf = wave_sum(tf);
+            tb = wave_sum(tb);
+            if (lane == 0) {
+                fw[m] = logw[m] + tf;   // alpha_m(xi, v)
+                bw[m] = logw[m] + tb;   // alpha_m(v, xi)
+            }
+        }
+        if (lane == 0) {
+            double mf = -INFINITY, mb = -INFINITY;
+            for (int m = 0; m < M; ++m) { mf = fmax(mf, fw[m]); mb = fmax(mb, bw[m]); }
+            double sf = 0.0, sb = 0.0;
+            for (int m = 0; m < M; ++m) { sf += exp(fw[m] - mf); sb += exp(bw[m] - mb); }
+            logr[n] = (mf + log(sf)) - (mb + log(sb));
+        }
+    }
+}
+
+hipError_t launch_propose(int64_t N, int K, int kr, int M, const int32_t* active, const int32_t* slot,
+                          const double* logw, const double* mean, const double* scale, double beta,
+                          uint64_t seed, uint64_t ctr, const double* xi, double* v, double* logr, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    propose_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, kr, M, active, slot, logw, mean, scale, beta, seed,
+                                                           ctr, xi, v, logr);
+    return hipGetLastError();
+}
+
+// Metropolis-Hastings decision (Alg. 2): log a = min(0, tau (Phi(xi) - Phi(v)) + log R);
+// accept iff log U_acc < log a; a proposal without a finite potential is rejected.
+__global__ __launch_bounds__(256) void accept_kernel(int K, double tau, uint64_t seed, uint64_t ctr,
+                                                     const double* __restrict__ v, const double* __restrict__ logr,
+                                                     const double* __restrict__ phinew, double* __restrict__ xi,
+                                                     double* __restrict__ phi, int32_t* __restrict__ n_acc) {
+    __shared__ int acc;
+    const int64_t n = blockIdx.x;
+    if (threadIdx.x == 0) {
+        const uint4 w = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const double ua = res53(w.z, w.w);
+        const double pn = phinew[n];
+        bool ok = false;
+        if (isfinite(pn)) {
+            const double la = fmin(0.0, tau * (phi[n] - pn) + logr[n]);
+            ok = log(ua) < la;
+        }
+        acc = ok;
+        if (ok) {
+            phi[n] = pn;
+            n_acc[n] += 1;
+        }
+    }
+    __syncthreads();
+    if (acc) {
+        for (int k = threadIdx.x; k < K; k += 256) xi[n * K + k] = v[n * K + k];
+    }
+}
+
+hipError_t launch_accept(int64_t N, int K, double tau, uint64_t seed, uint64_t ctr, const double* v,
+                         const double* logr, const double* phinew, double* xi, double* phi, int32_t* n_acc,
+                         hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    accept_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, tau, seed, ctr, v, logr, phinew, xi, phi, n_acc);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(int64_t N, int K, const int32_t* __restrict__ idx,
+                                                     const double* __restrict__ xi_in,
+                                                     const double* __restrict__ phi_in, double* __restrict__ xi_out,
+                                                     double* __restrict__ phi_out) {
+    const int64_t n = blockIdx.x;
+    const int64_t src = idx[n];
+    if (src < 0 || src >= N) return;   // indices come from smc_resample; others leave the row untouched
+    for (int k = threadIdx.x; k < K; k += 256) xi_out[n * K + k] = xi_in[src * K + k];
+    if (threadIdx.x == 0 && phi_in && phi_out) phi_out[n] = phi_in[src];
+}
+
+hipError_t launch_gather(int64_t N, int K, const int32_t* idx, const double* xi_in, const double* phi_in,
+                         double* xi_out, double* phi_out, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    gather_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(N, K, idx, xi_in, phi_in, xi_out, phi_out);
+    return hipGetLastError();
+}
+
+}  // namespace smc

@@ -1,0 +1,77 @@
+"""The C ABI library builds, loads and exports what include/smc.h declares (CPU only).
+
+No call here reaches the device: the only calls made are ones whose host-side validation
+rejects the arguments before anything is launched.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "smc.h")
+
+
+@pytest.fixture(scope="module")
+def libsmc():
+    from paper_2503_16028_amd import build, smc
+    if not os.path.exists(smc.LIB_PATH):
+        build.build()
+    return smc.lib()
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(smc_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_calls():
+    names = declared()
+    for n in ("smc_prior_sample", "smc_forward_batch", "smc_potential", "smc_gmpcn_move", "smc_temper",
+              "smc_resample"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(libsmc):
+    from paper_2503_16028_amd import smc
+    for n in declared():
+        assert hasattr(libsmc, n), n
+    assert sorted(declared()) == smc.EXPORTED
+
+
+def test_host_validation_rejects_without_launching(libsmc):
+    from paper_2503_16028_amd import smc
+    c_vp = ctypes.c_void_p
+    null = c_vp()
+    assert libsmc.smc_temper(0, null, null, 0.5, null, null, null, null, null, null) == -1
+    assert b"N must be" in libsmc.smc_last_error()
+    assert libsmc.smc_temper(4, c_vp(8), c_vp(8), 1.5, c_vp(8), c_vp(8), c_vp(8), c_vp(8), null, null) == -1
+    assert libsmc.smc_resample(16385, c_vp(8), 0, c_vp(8), null, null) == -1
+    assert libsmc.smc_resample(4, c_vp(8), 1 << 53, c_vp(8), null, null) == -1
+    assert libsmc.smc_gather(4, 8, c_vp(8), c_vp(16), null, c_vp(16), null, null) == -1   # aliasing
+    assert libsmc.smc_problem_create(None, None) == -1
+    d = smc.ProblemDesc()
+    d.dim = 3
+    h = c_vp()
+    assert libsmc.smc_problem_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"dim" in libsmc.smc_last_error()
+    d.dim, d.n_levels = 2, 1
+    d.grid_n[0] = 100                                          # not a power of two
+    assert libsmc.smc_problem_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert libsmc.smc_problem_info(None, None, None, None) == -1
+
+
+def test_observation_must_be_a_node(libsmc):
+    from paper_2503_16028_amd import smc
+    d = smc.ProblemDesc()
+    d.dim, d.n_levels, d.kl, d.kr, d.n_obs, d.obs_den = 2, 1, 8, 8, 1, 128
+    d.grid_n[0] = 64
+    obs = (ctypes.c_int32 * 2)(3, 64)                         # 3/128 is not a node of the 64 grid
+    y = (ctypes.c_double * 1)(0.1)
+    d.obs_num, d.y, d.sigma, d.f, d.n_max = obs, y, 0.01, 1.0, 4
+    d.tol64, d.tol_inner, d.max_iter, d.max_sweeps = 1e-10, 1e-5, 100, 4
+    h = ctypes.c_void_p()
+    assert libsmc.smc_problem_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"not a node" in libsmc.smc_last_error()

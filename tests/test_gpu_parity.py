@@ -1,0 +1,350 @@
+"""Parity of every C ABI call with the oracle on identical seeded inputs (GPU).
+
+Tolerances: FP64 path 1e-10 relative; FP32+refinement 1e-4 relative on potentials;
+integer work (resampling indices, accept counts) bit-exact.
+"""
+import json
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from conftest import golden
+from oracle import philox
+from oracle.forward import observe, potential, solve
+from oracle.moves import GM, gmpcn_moves, pcn_gm
+from oracle.problem import Problem as OProblem, synthesize
+from oracle.resample import systematic
+from oracle.temper import temper
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    d = json.load(open(golden("problem_%s.json" % name)))
+    return d, OProblem(d)
+
+
+def gpu_problem(d, n_max, grids=None, **kw):
+    from paper_2503_16028_amd import smc
+    return smc.Problem(d, n_max, grids=grids, **kw)
+
+
+def t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def oracle_G(op, xi, n):
+    return np.array([observe(op, solve(op, synthesize(op, x, n), n), n) for x in xi])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2503_16028_amd import smc
+    smc.lib()
+    assert torch.cuda.is_available()
+
+
+# ------------------------------------------------------------------ synthesis and draws
+
+@pytest.mark.parametrize("name,grid,N", [("t2", 16, 5), ("t2", 64, 3), ("c3", 128, 3), ("c5", 256, 2),
+                                         ("t1", 64, 4), ("c1", 64, 3)])
+def test_synthesis(name, grid, N):
+    from paper_2503_16028_amd import smc
+    banner("synthesis", name, grid, N)
+    d, op = load(name)
+    p = gpu_problem(d, N, grids=[grid])
+    xi = inputs.particles(N, op.K, 1)
+    u = torch.empty(N, (grid + 1) ** op.dim, dtype=torch.float64, device=DEV)
+    smc.smc_synthesize(p, N, t(xi), 0, u)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    for k in range(N):
+        U = synthesize(op, xi[k], grid)
+        ref = U.T.reshape(-1) if op.dim == 2 else U
+        assert np.abs(got[k] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_prior_sample_matches_generator():
+    from paper_2503_16028_amd import smc
+    banner("prior sample")
+    d, op = load("c3")
+    N = 33
+    p = gpu_problem(d, N)
+    xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    smc.smc_prior_sample(p, N, 2503, 17, xi)
+    ref = philox.normals(2503, 17, np.arange(N), op.K)
+    assert np.abs(xi.cpu().numpy() - ref).max() < 1e-13
+
+
+# ------------------------------------------------------------------ forward map and potential
+
+FWD_CASES = [("t2", 16, 13), ("t2", 32, 13), ("t2", 64, 7), ("c2", 64, 5), ("c3", 128, 4), ("c5", 256, 2)]
+# FP64 residual tolerance each grid can certify: evaluating f - A w in FP64 carries rounding of
+# about eps |A| |w| / |f|, and |A| grows like 8 / h^2 (1e-12 relative at 128^2)
+TOL64 = {16: 1e-13, 32: 1e-13, 64: 1e-13, 128: 2e-12, 256: 6e-12}
+
+
+@pytest.mark.parametrize("name,grid,N", FWD_CASES)
+def test_forward_fp64(name, grid, N):
+    from paper_2503_16028_amd import smc
+    banner("forward fp64", name, grid, N)
+    d, op = load(name)
+    p = gpu_problem(d, N, grids=[grid], tol64=TOL64[grid], max_iter=60 * grid, max_sweeps=6)
+    xi = inputs.particles(N, op.K, 2)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP64, G, it)
+    torch.cuda.synchronize()
+    ref = oracle_G(op, xi, grid)
+    assert (it.cpu().numpy() > 0).all()
+    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert smc.smc_status_flags(p) == 0
+
+
+@pytest.mark.parametrize("name,grid,N", FWD_CASES)
+def test_forward_fp32_refine(name, grid, N):
+    from paper_2503_16028_amd import smc
+    banner("forward fp32+refine", name, grid, N)
+    d, op = load(name)
+    p = gpu_problem(d, N, grids=[grid], tol64=1e-10, tol_inner=1e-5, max_iter=80 * grid)
+    xi = inputs.particles(N, op.K, 3)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP32_REFINE, G)
+    smc.smc_potential(p, N, G, phi)
+    torch.cuda.synchronize()
+    ref = oracle_G(op, xi, grid)
+    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    ref_phi = potential(ref, op.y, op.sigma)
+    assert np.abs(phi.cpu().numpy() / ref_phi - 1).max() <= 1e-4
+
+
+@pytest.mark.parametrize("name,grid", [("t1", 16), ("t1", 64), ("c1", 64)])
+def test_forward_1d(name, grid):
+    from paper_2503_16028_amd import smc
+    banner("forward 1d", name, grid)
+    d, op = load(name)
+    N = 37
+    p = gpu_problem(d, N, grids=[grid])
+    xi = inputs.particles(N, op.K, 4)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP64, G)
+    torch.cuda.synchronize()
+    ref = oracle_G(op, xi, grid)
+    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_potential():
+    from paper_2503_16028_amd import smc
+    banner("potential")
+    d, op = load("c2")
+    N = 300
+    p = gpu_problem(d, N)
+    G = 0.05 + 0.01 * inputs.particles(N, op.n_obs, 5)
+    G[7, 3] = np.nan
+    G[9, 0] = np.inf
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_potential(p, N, t(G), phi)
+    ref = potential(G, op.y, op.sigma)
+    got = phi.cpu().numpy()
+    assert np.isinf(got[7]) and np.isinf(got[9])
+    fin = np.isfinite(ref)
+    assert np.abs(got[fin] / ref[fin] - 1).max() < 1e-13
+
+
+def test_batch_invariance_and_determinism():
+    """A particle solved alone gives the same bits as inside a batch, and runs repeat."""
+    from paper_2503_16028_amd import smc
+    banner("batch invariance")
+    d, op = load("c2")
+    N = 16
+    p = gpu_problem(d, N)
+    xi = t(inputs.particles(N, op.K, 6))
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G)
+    G2 = torch.empty_like(G)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G2)
+    one = torch.empty(1, op.n_obs, dtype=torch.float64, device=DEV)
+    for k in (0, 5, 15):
+        smc.smc_forward_batch(p, 1, xi[k:k + 1].contiguous(), None, smc.SMC_FP32_REFINE, one)
+        assert torch.equal(one[0], G[k])
+    assert torch.equal(G, G2)
+
+
+def test_nonconvergence_is_reported_and_rejected():
+    from paper_2503_16028_amd import smc
+    banner("non-convergence")
+    d, op = load("t2")
+    N = 6
+    p = gpu_problem(d, N, grids=[32], max_iter=3, max_sweeps=2)
+    xi = t(inputs.particles(N, op.K, 7))
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G, it)
+    assert (it.cpu().numpy() == -1).all() and torch.isnan(G).all()
+    assert smc.smc_status_flags(p) & smc.FLAG_NOCONV
+    phi = torch.zeros(N, dtype=torch.float64, device=DEV)
+    n_acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    xi0 = xi.clone()
+    smc.smc_gmpcn_move(p, N, (t([0.0]), t(np.zeros((1, op.kr))), t(np.ones((1, op.kr)))), 0.3, 1.0, 2, 1, 1,
+                       None, smc.SMC_FP32_REFINE, xi, phi, n_acc)
+    assert (n_acc.cpu().numpy() == 0).all() and torch.equal(xi, xi0)
+
+
+# ------------------------------------------------------------------ moves
+
+def _move_case(name, grid, N, M, beta, tau, n_moves, prec, seed):
+    from paper_2503_16028_amd import smc
+    d, op = load(name)
+    tol = dict(tol64=1e-13, max_iter=60 * grid, max_sweeps=6) if prec == 0 else dict(tol64=1e-10)
+    p = gpu_problem(d, N, grids=[grid], **tol)
+    assert list(p.active) == list(op.active())
+    xi0 = inputs.particles(N, op.K, seed, 0.8)
+    phi0 = potential(oracle_G(op, xi0, grid), op.y, op.sigma)
+    if M == 0:
+        gm = pcn_gm(op.K, op.active())
+    else:
+        logw, mean, scale = inputs.mixture(M, op.kr, seed + 1, spread=0.5)
+        gm = GM(logw, mean, scale, op.active(), op.K)
+    xi = t(xi0)
+    phi = t(phi0)
+    n_acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_gmpcn_move(p, N, (t(gm.logw), t(gm.mean), t(gm.scale)), beta, tau, n_moves, seed, 1000 + seed, None,
+                       prec, xi, phi, n_acc)
+    torch.cuda.synchronize()
+    rx, rphi, racc = gmpcn_moves(op, grid, xi0, phi0, gm, beta, tau, n_moves, seed, 1000 + seed)
+    return xi.cpu().numpy(), phi.cpu().numpy(), n_acc.cpu().numpy(), rx, rphi, racc
+
+
+@pytest.mark.parametrize("name,grid,N,M,beta,tau,n_moves", [
+    ("t2", 32, 24, 3, 0.4, 0.7, 3),
+    ("t2", 16, 40, 0, 0.5, 1.0, 2),       # plain pCN
+    ("t2", 32, 16, 4, 1.0, 0.5, 2),       # beta = 1: mixture independence sampler
+    ("t1", 64, 50, 0, 0.3, 1.0, 4),       # 1D pCN (the 1D workload's kernel)
+    ("c2", 64, 6, 4, 0.2, 0.6, 2),
+])
+def test_move_fp64(name, grid, N, M, beta, tau, n_moves):
+    banner("move fp64", name, grid, N, M, beta, tau, n_moves)
+    xi, phi, acc, rx, rphi, racc = _move_case(name, grid, N, M, beta, tau, n_moves, 0, 11)
+    assert np.array_equal(acc, racc)
+    assert 0 < acc.sum()
+    assert np.abs(xi - rx).max() <= 1e-10 * np.abs(rx).max()
+    assert np.abs(phi / rphi - 1).max() <= 1e-9
+
+
+def test_move_fp32_refine():
+    banner("move fp32+refine")
+    xi, phi, acc, rx, rphi, racc = _move_case("t2", 64, 12, 3, 0.3, 0.8, 2, 1, 12)
+    assert np.array_equal(acc, racc)
+    assert np.abs(phi / rphi - 1).max() <= 1e-4
+
+
+# ------------------------------------------------------------------ tempering and resampling
+
+@pytest.mark.parametrize("N,tau", [(1, 0.0), (7, 0.3), (1000, 0.0), (4096, 0.55)])
+def test_temper(N, tau):
+    from paper_2503_16028_amd import smc
+    banner("temper", N, tau)
+    phi0 = inputs.potentials(N, 30 + N)
+    if N > 10:
+        phi0[3] = np.inf
+        phi0[5] = np.nan
+    h, tau_new, W, lz = (torch.empty(1, dtype=torch.float64, device=DEV) for _ in range(4))
+    Wt = torch.empty(N, dtype=torch.float64, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    smc.smc_temper(N, t(phi0), t([tau]), 0.5, h, tau_new, Wt, lz, flags)
+    rh, rtau, rW, rlz, stalled = temper(phi0, tau, 0.5)
+    assert h.item() == pytest.approx(rh, rel=1e-10, abs=1e-300)
+    assert tau_new.item() == pytest.approx(rtau, rel=1e-12)
+    assert lz.item() == pytest.approx(rlz, rel=1e-10, abs=1e-10)
+    assert np.abs(Wt.cpu().numpy() - rW).max() <= 1e-10 * rW.max()
+    assert flags.item() == 0
+
+
+def test_temper_edge_cases():
+    from paper_2503_16028_amd import smc
+    banner("temper edges")
+    h, tau_new, lz = (torch.empty(1, dtype=torch.float64, device=DEV) for _ in range(3))
+    W = torch.empty(64, dtype=torch.float64, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    smc.smc_temper(64, t(np.full(64, 3.0)), t([0.25]), 0.5, h, tau_new, W, lz, flags)
+    assert h.item() == 0.75 and tau_new.item() == 1.0 and flags.item() == 0
+    stall = np.full(64, 1e308)
+    stall[3] = 0.0
+    smc.smc_temper(64, t(stall), t([0.0]), 0.5, h, tau_new, W, lz, flags)
+    assert h.item() == 0.0 and flags.item() & smc.FLAG_STALL
+    flags.zero_()
+    smc.smc_temper(64, t(np.full(64, np.inf)), t([0.0]), 0.5, h, tau_new, W, lz, flags)
+    assert flags.item() & smc.FLAG_NONFINITE
+
+
+@pytest.mark.parametrize("N", [1, 7, 1000, 4096, 16384])
+@pytest.mark.parametrize("kind", ["dirichlet", "sparse", "one", "uniform"])
+def test_resample_bit_exact(N, kind):
+    from paper_2503_16028_amd import smc
+    banner("resample", N, kind)
+    W = inputs.weights(N, N + 3, kind)
+    u = inputs.u53(N)
+    idx = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_resample(N, t(W), u, idx)
+    assert idx.cpu().numpy().tolist() == systematic(W, u)
+
+
+def test_gather():
+    from paper_2503_16028_amd import smc
+    banner("gather")
+    N, K = 500, 1024
+    W = inputs.weights(N, 40)
+    idx = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_resample(N, t(W), inputs.u53(40), idx)
+    xi = t(inputs.particles(N, K, 41))
+    phi = t(inputs.potentials(N, 42))
+    xo = torch.empty_like(xi)
+    po = torch.empty_like(phi)
+    smc.smc_gather(N, K, idx, xi, phi, xo, po)
+    ii = idx.long().cpu()
+    assert torch.equal(xo.cpu(), xi.cpu()[ii]) and torch.equal(po.cpu(), phi.cpu()[ii])
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+def test_full_size_metric_configuration_sampled():
+    """128^2, N = 4096, FP32 + refinement, in the launch configuration the benchmark times:
+    one move for every particle; sampled particles replayed by the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("full size 128^2 N=4096")
+    d, op = load("c3")
+    N = 4096
+    p = gpu_problem(d, N, tol64=1e-10, tol_inner=1e-5)
+    xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    smc.smc_prior_sample(p, N, 2503, 0, xi)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G, it)
+    smc.smc_potential(p, N, G, phi)
+    xi_h = xi.cpu().numpy()
+    phi_h = phi.cpu().numpy()
+    assert (it.cpu().numpy() > 0).all() and np.isfinite(phi_h).all()
+    pick = [0, 1, 777, 2048, 4095]
+    ref = potential(oracle_G(op, xi_h[pick], 128), op.y, op.sigma)
+    assert np.abs(phi_h[pick] / ref - 1).max() <= 1e-4
+    logw, mean, scale = inputs.mixture(8, op.kr, 43, spread=0.5)
+    n_acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_gmpcn_move(p, N, (t(logw), t(mean), t(scale)), 0.2, 0.05, 1, 9, 500, None, smc.SMC_FP32_REFINE, xi,
+                       phi, n_acc)
+    gm = GM(logw, mean, scale, op.active(), op.K)
+    rx, rphi, racc = gmpcn_moves(op, 128, xi_h[pick], phi_h[pick], gm, 0.2, 0.05, 1, 9, 500, ids=pick)
+    assert np.array_equal(n_acc.cpu().numpy()[pick], racc)
+    assert np.abs(xi.cpu().numpy()[pick] - rx).max() <= 1e-6
+    assert np.abs(phi.cpu().numpy()[pick] / rphi - 1).max() <= 1e-4
