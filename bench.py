@@ -104,14 +104,14 @@ def main():
             s.tau.copy_(s.tau_new)
             tau = float(s.tau.item())
             t1 = time.perf_counter()
-            X = s.xi[:, s.active].cpu().numpy()          # stage input: mixture fit (not timed)
+            X = s.xi.cpu().numpy()[:, p.active]          # stage input: mixture fit (not timed)
             logw, mean, var = fit_mixture(X, M, s.seed + s.stage, iters=20)
             gm = tuple(torch.tensor(a, dtype=torch.float64, device=dev).contiguous() for a in (logw, mean, var))
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             smc.smc_gmpcn_move(p, N, gm, s.beta, tau, n_moves, s.seed, s.stage << 20, None, prec, s.xi, s.phi,
                                s.n_acc)
-            rate = float(s.n_acc.sum().item()) / (N * n_moves)
+            rate = float(s.n_acc.cpu().numpy().sum()) / (N * n_moves)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             s.beta = min(1.0, 2 * s.beta) if rate > 0.3 else (0.5 * s.beta if rate < 0.15 else s.beta)

@@ -92,7 +92,7 @@ class SMCSampler:
     def mixture(self):
         if self.M == 1:
             return pcn_mixture(self.p.kr, self.dev)
-        X = self.xi[:, self.active].cpu().numpy()
+        X = self.xi.cpu().numpy()[:, self.p.active]
         logw, mean, var = fit_mixture(X, self.M, self.seed + self.stage)
         t = lambda a: torch.tensor(a, dtype=torch.float64, device=self.dev).contiguous()
         return t(logw), t(mean), t(var)
@@ -113,7 +113,7 @@ class SMCSampler:
         gm = self.mixture()
         smc.smc_gmpcn_move(p, N, gm, self.beta, tau, self.n_moves, self.seed, base, None, self.prec, self.xi,
                            self.phi, self.n_acc)
-        rate = float(self.n_acc.sum().item()) / (N * max(1, self.n_moves))
+        rate = float(self.n_acc.cpu().numpy().sum()) / (N * max(1, self.n_moves))
         self.log_Z += float(self.log_z.item())
         self.history.append(dict(stage=self.stage, tau=tau, h=float(self.h.item()), beta=self.beta, rate=rate))
         if rate > 0.3:
