@@ -78,7 +78,14 @@ typedef struct {
     double tol_inner;       /* FP32 inner solves reduce their residual by this factor */
     int32_t max_iter;       /* cap on conjugate-gradient iterations per solve (all sweeps) */
     int32_t max_sweeps;     /* cap on FP64 refinement sweeps per solve */
+    int32_t precond;        /* SMC_PRECOND_AUTO or SMC_PRECOND_JACOBI */
 } smc_problem_desc;
+
+/* Preconditioner of the conjugate gradients.  AUTO: the fast-Poisson (sine-transform)
+ * preconditioner on the matrix cores for FP32 solves on 32^2, 64^2 and 128^2 grids, Jacobi
+ * scaling elsewhere; JACOBI: Jacobi scaling everywhere. */
+#define SMC_PRECOND_AUTO 0
+#define SMC_PRECOND_JACOBI 1
 
 /* Mixture {w_j, m_j, C_j} of Sec. 2.3 (C_j shares the prior's eigenfunctions), in whitened
  * coordinates over the kr active modes; all device pointers.
@@ -164,6 +171,13 @@ int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t
  * (phi pointers may be NULL).  Outputs must not alias inputs. */
 int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
                const double* phi_in, double* xi_out, double* phi_out, smc_stream stream);
+
+/* The fast-Poisson preconditioner of the forward solves by itself (for tests): for each of N
+ * grids, z = L^{-1} r with L the constant-coefficient Dirichlet Laplacian of grid `level`, up
+ * to a positive constant factor, computed with bf16 sine transforms on the matrix cores.
+ * r, z: [N][n][n] FP32, element [g][c] for the node ((c+1)/n, (g+1)/n); index n-1 is boundary
+ * padding and must hold 0 in r.  Only grids of 32, 64 and 128 intervals. */
+int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z, smc_stream stream);
 
 /* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by
  * smc_forward_batch and smc_gmpcn_move on p is then bracketed by two HIP events recorded on

@@ -52,7 +52,7 @@ static hipError_t upload(T** dst, const T* src, size_t n) {
 
 static void free_problem(Problem& P) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
-    for (int l = 0; l < MAX_LEVELS; ++l) { f(P.lv[l].basis); f(P.lv[l].obs_node); }
+    for (int l = 0; l < MAX_LEVELS; ++l) { f(P.lv[l].basis); f(P.lv[l].obs_node); f(P.lv[l].dst_S); f(P.lv[l].dst_lam); }
     f(P.sqrt_lam); f(P.active); f(P.slot); f(P.y);
     f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_sd); f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.flags); f(P.stats);
@@ -80,6 +80,8 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     if (!(d->tol64 > 0.0) || !(d->tol_inner > 0.0 && d->tol_inner < 1.0))
         return fail(SMC_E_INVAL, "tolerances must be positive (tol_inner < 1)");
     if (d->max_iter < 1 || d->max_sweeps < 1) return fail(SMC_E_INVAL, "max_iter and max_sweeps must be >= 1");
+    if (d->precond != SMC_PRECOND_AUTO && d->precond != SMC_PRECOND_JACOBI)
+        return fail(SMC_E_INVAL, "unknown preconditioner %d", d->precond);
     for (int k = 0; k < d->n_obs; ++k) {
         if (!std::isfinite(d->y[k])) return fail(SMC_E_INVAL, "y[%d] is not finite", k);
         for (int a = 0; a < d->dim; ++a) {
@@ -106,6 +108,7 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     P.tol_inner = d->tol_inner;
     P.max_iter = d->max_iter;
     P.max_sweeps = d->max_sweeps;
+    P.precond = d->precond;
     P.n_max = d->n_max;
 
     // prior: sqrt(lambda) and the active modes (largest lambda first, ties to the lower index)
@@ -167,6 +170,23 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
             }
         }
         ck(upload(&P.lv[l].obs_node, nodes.data(), nodes.size()));
+        if (P.dim == 2 && dst_supported(n)) {
+            // S[a][b] = sqrt(2/n) sin(pi (a+1)(b+1) / n) for nodes a+1, b+1 = 1..n; the last row and
+            // column (the boundary padding node n) are exactly zero
+            std::vector<__bf16> S((size_t)n * n);
+            std::vector<float> lam(n);
+            for (int r = 0; r < n; ++r) {
+                lam[r] = (float)std::pow(std::sin(M_PI * (r + 1) / (2.0 * n)), 2);
+                for (int q = 0; q < n; ++q) {
+                    const double v = (r == n - 1 || q == n - 1)
+                                         ? 0.0
+                                         : std::sqrt(2.0 / n) * std::sin(M_PI * (double)((r + 1) * (q + 1)) / n);
+                    S[(size_t)r * n + q] = (__bf16)(float)v;
+                }
+            }
+            ck(upload((__bf16**)&P.lv[l].dst_S, S.data(), S.size()));
+            ck(upload(&P.lv[l].dst_lam, lam.data(), lam.size()));
+        }
     }
     const int64_t nb = P.n_big;
     P.e_stride = P.dim == 2 ? (nb + 1) * (nb + 1) : nb + 1;
@@ -339,7 +359,13 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     a.iters = iters;
     a.stats = P.profiling ? P.stats : nullptr;
     if (P.profiling && (e = record(ps->pool, s)) != hipSuccess) return e;
-    e = (P.dim == 2) ? launch_solve2d(P.lv[level].n, prec, N, a, s) : launch_solve1d(P.lv[level].n, N, a, s);
+    const Level& L = P.lv[level];
+    if (P.dim == 1)
+        e = launch_solve1d(L.n, N, a, s);
+    else if (prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S)
+        e = launch_solve2d_dst(L.n, N, a, L.dst_S, L.dst_lam, s);
+    else
+        e = launch_solve2d(L.n, prec, N, a, s);
     if (e != hipSuccess) return e;
     if (P.profiling) e = record(ps->pool, s);
     return e;
@@ -390,6 +416,18 @@ extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double
         HIPCHK(forward(p, 0, prec, N, P.ws_v, nullptr, P.ws_phinew, P.ws_iters, s));
         HIPCHK(launch_accept(N, P.K, tau, seed, c, P.ws_v, P.ws_logr, P.ws_phinew, xi, phi, n_acc, s));
     }
+    return SMC_OK;
+}
+
+extern "C" int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z,
+                                 smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int rc = check_n(p->P, N)) return rc;
+    if (level < 0 || level >= p->P.n_levels) return fail(SMC_E_INVAL, "level %d out of range", level);
+    const Level& L = p->P.lv[level];
+    if (!L.dst_S) return fail(SMC_E_INVAL, "grid %d has no fast-Poisson preconditioner", L.n);
+    if (N > 0 && (!r || !z)) return fail(SMC_E_INVAL, "r and z must not be NULL");
+    HIPCHK(launch_dst_apply(L.n, N, r, z, L.dst_S, L.dst_lam, (hipStream_t)stream));
     return SMC_OK;
 }
 

@@ -18,6 +18,8 @@ struct Level {
     int n = 0;                   // intervals per axis
     double* basis = nullptr;     // 2D: [(n+1)][KLP] c_k cos(k pi i / n); 1D: [(n+1)][kl] sqrt2 sin(k pi i / n)
     int32_t* obs_node = nullptr; // [n_obs] flat nodal index (2D j*(n+1)+i, 1D i)
+    void* dst_S = nullptr;       // [n][n] bf16 sine transform (fast-Poisson preconditioner)
+    float* dst_lam = nullptr;    // [n] its 1D eigenvalues sin^2(pi (k+1) / 2n)
 };
 
 struct Problem {
@@ -25,7 +27,7 @@ struct Problem {
     Level lv[MAX_LEVELS];
     int n_big = 0;               // largest grid
     double sigma = 1, f = 1, tol64 = 1e-10, tol_inner = 1e-5;
-    int max_iter = 0, max_sweeps = 0;
+    int max_iter = 0, max_sweeps = 0, precond = 0;
     int64_t n_max = 0;
     double* sqrt_lam = nullptr;  // [K]
     int32_t* active = nullptr;   // [kr] active mode ids
@@ -137,6 +139,10 @@ hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, cons
                           int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
 hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStream_t s);
 hipError_t launch_solve1d(int n, int64_t N, const SolveArgs& a, hipStream_t s);
+bool dst_supported(int n);
+hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s);
+hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
+                            hipStream_t s);
 
 hipError_t launch_prior(int64_t N, int K, uint64_t seed, uint64_t ctr, double* xi, hipStream_t s);
 hipError_t launch_potential(int64_t N, int n_obs, const double* G, const double* y, double inv2s2, double* phi,

@@ -1,102 +1,231 @@
 // Forward solve of the Darcy problem, one workgroup per particle.
 //
-// Operator (flux form, h = 1/n, geometric-mean faces):
+// Operator (flux form, h = 1/n, geometric-mean faces, Sec. 3.2 eq. (example2:PDE)):
 //   (A w)_P = sum_Q a_PQ (w_P - w_Q) / h^2,   a_PQ = e_P e_Q,  e = exp(u/2),
-// at interior nodes, w = 0 on the boundary; the PDE is -div(e^u grad w) = f (Sec. 3.2).
+// at interior nodes, w = 0 on the boundary.  Because every face coefficient is a product, the
+// symmetrically Jacobi-scaled operator factorises:
+//   A^ = D^{-1/2} A D^{-1/2} = I - T N T,   t_P = sqrt(e_P / sum_{Q nbr P} e_Q),
+// with N the 0/1 adjacency of interior nodes.  So one coefficient per node suffices and
+//   (A^ p)_P = p_P - t_P (y_E + y_W + y_N + y_S),   y = t p.
 //
-// Method: conjugate gradients on the symmetrically Jacobi-scaled system
-//   A^ y = D^{-1/2} r,  A^ = D^{-1/2} A D^{-1/2},  D = diag(A),
-// (unit diagonal, so the preconditioner costs nothing), run inside an FP64 residual
-// refinement loop: each sweep forms r = f - A x with the FP64 operator, solves the scaled
-// correction in precision T to a relative reduction, and adds it to the FP64 iterate.  The
-// loop stops on the FP64 residual, ||f - A x|| <= tol64 ||f||, so the accuracy is set by the
-// FP64 operator whatever T is.
+// Method: preconditioned conjugate gradients on A^ y = D^{-1/2} r in precision T, inside an
+// FP64 residual refinement: each sweep forms r = f - A x with the FP64 operator, solves the
+// scaled correction to a relative reduction, and adds D^{-1/2} y to the FP64 iterate; the
+// loop stops on ||f - A x|| <= tol64 ||f||, so the accuracy is the FP64 operator's whatever T.
+// Preconditioners: none beyond the Jacobi scaling, or (DST) the inverse of the constant-
+// coefficient Dirichlet Laplacian L, which A^ is spectrally close to (its iteration count does
+// not grow with the grid).  L^{-1} = S diag(1 / (lam_k + lam_l)) S with the orthonormal
+// symmetric sine transform S[a][b] = sqrt(2/n) sin(pi (a+1)(b+1) / n) and
+// lam_k = sin^2(pi (k+1) / (2n)) up to a constant factor (CG is blind to it), applied as four
+// 16x16x32 bf16 MFMA products with FP32 accumulation; bf16 rounding perturbs only the
+// preconditioner, never the operator or the FP64 residual.
 //
-// Data layout inside a workgroup (on-chip variant): thread t owns column c = t % n of the
-// padded n x n node block (x-node i = c + 1) and a strip of R consecutive rows
-// (y-nodes j = (t / n) R + 1 ..).  Nodes with i = n or j = n are boundary padding and stay 0.
-// Vertical neighbours are in the thread's registers; horizontal neighbours come through LDS:
-// every iteration each thread publishes p and s = a^_E p (the flux coefficient times p), so
-// the west term a^_W p_W of a node is read as one value written by its left neighbour.
-// Dot products are wave butterflies plus a fixed-order sum over waves: every thread sees the
-// same bits and a particle's result does not depend on the batch it is solved in.
+// On-chip layout: thread t owns column c = t % n of the padded n x n block (x-node c + 1) and a
+// strip of R rows (y-nodes (t / n) R + 1 ..); nodes with index n are boundary padding with t = 0
+// and p = 0.  The CG vectors and t live in registers; each iteration publishes y = t p to one
+// zero-padded LDS array, from which the horizontal neighbours (and the strip ends) are read at
+// immediate offsets with no branches.  Dot products are wave butterflies plus a fixed-order sum
+// of the wave partials: every thread sees the same bits, and a particle's result does not depend
+// on the batch it is solved in.
 #include "common.hpp"
 
 namespace smc {
 
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <typename T, int NN, int R>
-__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a) {
+// v_mfma_f32_16x16x32_bf16 lane layout, checked on the device:
+//   A[16][32]: lane supplies row lane % 16, k = 8 (lane / 16) + 0..7
+//   B[32][16]: lane supplies col lane % 16, k = 8 (lane / 16) + 0..7
+//   D[16][16]: lane holds col lane % 16, rows 4 (lane / 16) + 0..3
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NN, int NW>
+struct DstShape {
+    static constexpr int NB = NN / 16;        // 16 x 16 tiles per dimension
+    static constexpr int KS = NN / 32;        // k steps of 32
+    static constexpr int TPW = NB * NB / NW;  // output tiles per wave
+    static constexpr int LD = NN + 8;         // bf16 row stride (16-byte aligned, spreads banks)
+    static constexpr int LDZ = NN + 4;        // fp32 row stride of the result
+    static constexpr int BYTES = 2 * NN * LD * 2 + NN * LDZ * 4;
+};
+
+template <typename T, int NN, int R, int NW>
+__device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem, const __bf16* __restrict__ Stab,
+                                          const float* __restrict__ lamtab, int c, int b, int wave, int lane) {
+    using DS = DstShape<NN, NW>;
+    constexpr int LD = DS::LD, LDZ = DS::LDZ, KS = DS::KS, TPW = DS::TPW, NB = DS::NB;
+    __bf16* bufA = reinterpret_cast<__bf16*>(smem);   // R^T, later T2^T
+    __bf16* bufB = bufA + NN * LD;                    // T1, later T3
+    float* ZT = reinterpret_cast<float*>(bufB + NN * LD);
+    const int lr = lane & 15, lk = lane >> 4;
+    const int sb = wave % NB, wq = wave / NB;
+    bf8 sfrag[KS];   // rows sb*16.. of S (symmetric: also columns sb*16.. as a B operand)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+        sfrag[ks] = *reinterpret_cast<const bf8*>(Stab + (sb * 16 + lr) * NN + 32 * ks + 8 * lk);
+    const float lam_col = lamtab[sb * 16 + lr];
+    {   // stage R^T[c][g] = bf16(r): the thread's strip is contiguous
+        __bf16* dst = bufA + c * LD + b * R;
+        if constexpr (R % 8 == 0) {
+#pragma unroll
+            for (int r = 0; r < R; r += 8) {
+                bf8 v;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = (__bf16)(float)rin[r + q];
+                *reinterpret_cast<bf8*>(dst + r) = v;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r] = (__bf16)(float)rin[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tt = 0; tt < TPW; ++tt) {   // T1[k][c] = sum_g S[k][g] R[g][c]
+        const int cb = wq * TPW + tt;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc = mfma_bf16(sfrag[ks], *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk), acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bufB[(sb * 16 + 4 * lk + v) * LD + cb * 16 + lr] = (__bf16)acc[v];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tt = 0; tt < TPW; ++tt) {   // T2^T[l][k] = (sum_c T1[k][c] S[c][l]) / (lam_k + lam_l)
+        const int rb = wq * TPW + tt;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc = mfma_bf16(*reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk), sfrag[ks], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = rb * 16 + 4 * lk + v;
+            bufA[(sb * 16 + lr) * LD + k] = (__bf16)(acc[v] / (lamtab[k] + lam_col));
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tt = 0; tt < TPW; ++tt) {   // T3[g][l] = sum_k S[g][k] T2[k][l]
+        const int cb = wq * TPW + tt;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc = mfma_bf16(sfrag[ks], *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk), acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bufB[(sb * 16 + 4 * lk + v) * LD + cb * 16 + lr] = (__bf16)acc[v];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tt = 0; tt < TPW; ++tt) {   // ZT[c][g] = sum_l T3[g][l] S[l][c]
+        const int rb = wq * TPW + tt;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc = mfma_bf16(*reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk), sfrag[ks], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ZT[(sb * 16 + lr) * LDZ + rb * 16 + 4 * lk + v] = acc[v];
+    }
+    __syncthreads();
+}
+
+// The fast-Poisson preconditioner alone: z[g][c] = (L^{-1} r)[g][c] on the padded n x n block of
+// each of N grids (row g is y-node g+1, column c is x-node c+1; padding row/column zero).
+template <int NN, int R>
+__global__ __launch_bounds__(NN * NN / R) void dst_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
+                                                               const __bf16* __restrict__ Stab,
+                                                               const float* __restrict__ lamtab) {
+    constexpr int NT = NN * NN / R, NW = NT / 64;
+    __shared__ __align__(16) unsigned char smem[DstShape<NN, NW>::BYTES];
+    const int tid = threadIdx.x, c = tid % NN, b = tid / NN;
+    const int64_t base = (int64_t)blockIdx.x * NN * NN;
+    float r[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = rin[base + (b * R + k) * NN + c];
+    dst_apply<float, NN, R, NW>(r, smem, Stab, lamtab, c, b, tid >> 6, tid & 63);
+    const float* ZT = reinterpret_cast<const float*>(smem + 2 * NN * DstShape<NN, NW>::LD * 2);
+#pragma unroll
+    for (int k = 0; k < R; ++k) zout[base + (b * R + k) * NN + c] = ZT[c * DstShape<NN, NW>::LDZ + b * R + k];
+}
+
+hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
+                            hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+    switch (n) {
+        case 32: dst_apply_kernel<32, 4><<<dim3((unsigned)N), dim3(256), 0, s>>>(r, z, Sb, lam); break;
+        case 64: dst_apply_kernel<64, 8><<<dim3((unsigned)N), dim3(512), 0, s>>>(r, z, Sb, lam); break;
+        case 128: dst_apply_kernel<128, 16><<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NN, int R, bool DST>
+__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf16* __restrict__ Stab,
+                                                         const float* __restrict__ lamtab) {
     constexpr int NT = NN * NN / R;
     constexpr int NW = NT / 64;
     constexpr int NP1 = NN + 1;
-    using T2 = typename Vec2<T>::type;
-    // (p, s) pairs of the n x n block, with one zero row (plus one element) of padding on each
-    // side so that every neighbour read is in bounds: reads that fall on padding, on the
-    // boundary-padding column or row, or across a row end meet zero p or zero coefficients.
     constexpr int PAD = NN + 1;
-    __shared__ T2 lps[PAD + NN * NN + PAD];
+    using DS = DstShape<NN, NW>;
+    constexpr int XBYTES = (2 * PAD + NN * NN) * (int)sizeof(T);
+    constexpr int SMEM = (DST && DS::BYTES > XBYTES) ? DS::BYTES : XBYTES;
+    static_assert(!DST || (NN >= 32 && (DS::NB * DS::NB) % NW == 0 && NW % DS::NB == 0), "transform tiling");
+    __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ double red1[NW], red2[NW];
+    T* ly = reinterpret_cast<T*>(smem);
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = tid % NN, b = tid / NN;
     const int i = c + 1;
     const int64_t row = blockIdx.x;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
     double* sd = a.sd + row * a.x_stride;
-    const double inv_h2 = (double)NN * (double)NN;
-    // own node of row r: tb[NN + 1 + r * NN]; east +1, west -1, north/south +-NN
-    T2* tb = lps + PAD + b * R * NN + c - NN - 1;
-    for (int k = tid; k < PAD; k += NT) {
-        lps[k] = T2{T(0), T(0)};
-        lps[PAD + NN * NN + k] = T2{T(0), T(0)};
-    }
+    const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
+    // own node of row r: tb[NN + 1 + r * NN]; east +1, west -1, north +NN, south -NN
+    T* tb = ly + PAD + b * R * NN + c - NN - 1;
 
-    // ---- setup: Jacobi scaling and the scaled face coefficients.  The per-node work outside
-    // the conjugate-gradient loop runs as plain (not unrolled) loops that stage values through
-    // the thread's own LDS slots, so only the loop's register arrays stay live across it.
+    for (int k = tid; k < PAD; k += NT) {
+        ly[k] = T(0);
+        ly[PAD + NN * NN + k] = T(0);
+    }
+    // ---- setup: D^{-1/2} (FP64, workspace) and t (registers); work outside the CG loop runs
+    // as plain loops that stage through the thread's own LDS slots
 #pragma unroll 1
     for (int r = 0; r < R; ++r) {
         const int g = b * R + r, j = g + 1;
-        double v = 1.0;
+        double sdv = 1.0, tv = 0.0;
         if (c < NN - 1 && g < NN - 1) {
-            const double d = e[j * NP1 + i] *
-                             (e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i]) *
-                             inv_h2;
-            v = 1.0 / sqrt(d);
+            const double eP = e[j * NP1 + i];
+            const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i];
+            sdv = h / sqrt(eP * S);
+            tv = sqrt(eP / S);
         }
-        sd[g * NN + c] = v;
+        sd[g * NN + c] = sdv;
+        tb[NN + 1 + r * NN] = (T)tv;
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int r = 0; r < R; ++r) {
-        const int g = b * R + r, j = g + 1;
-        T vae = T(0), van = T(0);
-        if (c < NN - 1 && g < NN - 1) {
-            const double eP = e[j * NP1 + i], sP = sd[g * NN + c];
-            if (c + 1 < NN - 1) vae = (T)(eP * e[j * NP1 + i + 1] * inv_h2 * sP * sd[g * NN + c + 1]);
-            if (g + 1 < NN - 1) van = (T)(eP * e[(j + 1) * NP1 + i] * inv_h2 * sP * sd[(g + 1) * NN + c]);
-        }
-        tb[NN + 1 + r * NN] = T2{vae, van};
-    }
-    T ae[R], an[R];
+    T t[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const T2 v = tb[NN + 1 + r * NN];
-        ae[r] = v.x;
-        an[r] = v.y;
-    }
-    T anS = T(0);
-    {
-        const int g0 = b * R;
-        if (c < NN - 1 && g0 < NN - 1 && g0 >= 1)
-            anS = (T)(e[g0 * NP1 + i] * e[(g0 + 1) * NP1 + i] * inv_h2 * sd[(g0 - 1) * NN + c] * sd[g0 * NN + c]);
-    }
+    for (int r = 0; r < R; ++r) t[r] = tb[NN + 1 + r * NN];
     __syncthreads();
+
+    // z = L^{-1} r into ZT[c][g] (LDS), with the barriers of the four products
+    auto precondition = [&](const T (&rin)[R]) __attribute__((always_inline)) {
+        if constexpr (DST) dst_apply<T, NN, R, NW>(rin, smem, Stab, lamtab, c, b, wave, lane);
+    };
+    auto zval = [&](int r) __attribute__((always_inline)) -> T {
+        if constexpr (DST) {
+            const float* ZT = reinterpret_cast<const float*>(smem + 2 * NN * DS::LD * 2);
+            return (T)ZT[c * DS::LDZ + b * R + r];
+        } else {
+            return T(0);
+        }
+    };
 
     // ---- refinement sweeps
     const double fnorm = fabs(a.f) * (double)(NN - 1);
@@ -105,7 +234,6 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a) {
     T x[R], rv[R], p[R], q[R];
     for (int sweep = 0;; ++sweep) {
         sweeps = sweep;
-        // FP64 residual r = f - A x, scaled by D^{-1/2} into the thread's LDS slots
         double acc = 0.0;
 #pragma unroll 1
         for (int r = 0; r < R; ++r) {
@@ -119,53 +247,70 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a) {
                     const double xW = (c > 0) ? x64[g * NN + c - 1] : 0.0;
                     const double xN = (g + 1 < NN - 1) ? x64[(g + 1) * NN + c] : 0.0;
                     const double xS = (g > 0) ? x64[(g - 1) * NN + c] : 0.0;
-                    const double eP = e[j * NP1 + i];
-                    res -= eP * inv_h2 *
+                    res -= e[j * NP1 + i] * inv_h2 *
                            (e[j * NP1 + i + 1] * (xP - xE) + e[j * NP1 + i - 1] * (xP - xW) +
                             e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
                 }
                 acc += res * res;
                 out = (T)(sd[g * NN + c] * res);
             }
-            tb[NN + 1 + r * NN].x = out;
+            tb[NN + 1 + r * NN] = out;
         }
         const double rr64 = block_sum<NW>(acc, red2);
         if (sqrt(rr64) <= a.tol64 * fnorm) { ok = true; break; }
         if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
 
-        // inner conjugate gradients on the scaled system, in precision T
         double tacc = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            rv[r] = tb[NN + 1 + r * NN].x;
+            rv[r] = tb[NN + 1 + r * NN];
             x[r] = T(0);
-            p[r] = rv[r];
             tacc += (double)rv[r] * (double)rv[r];
         }
-        double rr = block_sum<NW>(tacc, red1);
+        double rr, rz;
+        if constexpr (DST) {
+            __syncthreads();                  // the transform buffers alias the staging slots
+            precondition(rv);
+            double zacc = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                p[r] = zval(r);
+                zacc += (double)rv[r] * (double)p[r];
+            }
+            rr = block_sum<NW>(tacc, red1);
+            rz = block_sum<NW>(zacc, red2);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = rv[r];
+            rr = block_sum<NW>(tacc, red1);
+            rz = rr;
+        }
         const double target = a.tol_inner * a.tol_inner * rr;
         bool broke = false;
         while (rr > target) {
             if (total >= a.max_iter) break;
 #pragma unroll
-            for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = T2{p[r], ae[r] * p[r]};
+            for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = t[r] * p[r];
+            if constexpr (DST) {   // the transform buffers alias the padding: zero it again
+                for (int k = tid; k < PAD; k += NT) {
+                    ly[k] = T(0);
+                    ly[PAD + NN * NN + k] = T(0);
+                }
+            }
             __syncthreads();
-            // q = A^ p: unit diagonal, east/north from p, west/south as published flux terms.
-            // Faces touching the boundary padding have zero coefficients and padding holds
-            // p = 0, so padding nodes get q = 0 with no branches.
             T pq_acc = T(0);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const T pE = tb[NN + 2 + r * NN].x;
-                const T sW = tb[NN + r * NN].y;
-                const T pN = (r + 1 < R) ? p[r + 1] : tb[NN + 1 + R * NN].x;
-                const T sS = (r > 0) ? an[r - 1] * p[r - 1] : anS * tb[1].x;
-                q[r] = p[r] - ae[r] * pE - sW - an[r] * pN - sS;
+                const T yE = tb[NN + 2 + r * NN];
+                const T yW = tb[NN + r * NN];
+                const T yN = (r + 1 < R) ? t[r + 1] * p[r + 1] : tb[NN + 1 + R * NN];
+                const T yS = (r > 0) ? t[r - 1] * p[r - 1] : tb[1];
+                q[r] = p[r] - t[r] * ((yE + yW) + (yN + yS));
                 pq_acc += p[r] * q[r];
             }
             const double pq = block_sum<NW>((double)pq_acc, red1);
             if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
-            const T alpha = (T)(rr / pq);
+            const T alpha = (T)(rz / pq);
             T r_acc = T(0);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -173,22 +318,38 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a) {
                 rv[r] -= alpha * q[r];
                 r_acc += rv[r] * rv[r];
             }
-            const double rrn = block_sum<NW>((double)r_acc, red2);
-            const T beta = (T)(rrn / rr);
-            rr = rrn;
-#pragma unroll
-            for (int r = 0; r < R; ++r) p[r] = rv[r] + beta * p[r];
+            rr = block_sum<NW>((double)r_acc, red2);
             ++total;
+            if (!(rr > target)) break;
+            if constexpr (DST) {
+                precondition(rv);
+                T z[R];
+                T rz_acc = T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    z[r] = zval(r);
+                    rz_acc += rv[r] * z[r];
+                }
+                const double rzn = block_sum<NW>((double)rz_acc, red1);
+                const T beta = (T)(rzn / rz);
+                rz = rzn;
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[r] = z[r] + beta * p[r];
+            } else {
+                const T beta = (T)(rr / rz);
+                rz = rr;
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[r] = rv[r] + beta * p[r];
+            }
         }
-        // x64 += D^{-1/2} y through the thread's own LDS slots (the stencil reads of other
-        // threads finished before the last reduction's barrier)
+        // x64 += D^{-1/2} y, staged through the thread's own LDS slots
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN].x = x[r];
+        for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = x[r];
 #pragma unroll 1
         for (int r = 0; r < R; ++r) {
             const int g = b * R + r;
-            const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN].x;
+            const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
             x64[g * NN + c] = (sweep == 0) ? corr : x64[g * NN + c] + corr;
         }
         __syncthreads();
@@ -221,8 +382,9 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a) {
     }
 }
 
-// Same method with every vector in global memory, for grids whose vectors do not fit in one
-// workgroup's registers and LDS.  1024 threads stride over the nodes of one particle.
+// Same method (Jacobi-scaled CG, product form) with every vector in global memory, for grids
+// whose vectors do not fit in one workgroup's registers and LDS; 1024 threads stride over
+// the nodes of one particle.
 template <typename T>
 __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
     constexpr int NW = 16;
@@ -235,37 +397,26 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
     double* x64 = a.x64 + row * a.x_stride;
     double* sd = a.sd + row * a.x_stride;
     T* vb = reinterpret_cast<T*>(reinterpret_cast<double*>(a.vec) + row * a.vec_stride);
-    T* ae = vb;
-    T* an = vb + nodes;
-    T* xv = vb + 2 * nodes;
-    T* rv = vb + 3 * nodes;
-    T* pv = vb + 4 * nodes;
-    T* qv = vb + 5 * nodes;
-    const double inv_h2 = (double)NN * (double)NN;
+    T* tv = vb;
+    T* xv = vb + nodes;
+    T* rv = vb + 2 * nodes;
+    T* pv = vb + 3 * nodes;
+    T* qv = vb + 4 * nodes;
+    T* yv = vb + 5 * nodes;
+    const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     auto interior = [&](int g, int c) { return c < NN - 1 && g < NN - 1; };
 
     for (int k = tid; k < nodes; k += 1024) {
         const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
-        double v = 1.0;
+        double sdv = 1.0, tt = 0.0;
         if (interior(g, c)) {
-            const double d = e[j * NP1 + i] *
-                             (e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i]) *
-                             inv_h2;
-            v = 1.0 / sqrt(d);
+            const double eP = e[j * NP1 + i];
+            const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i];
+            sdv = h / sqrt(eP * S);
+            tt = sqrt(eP / S);
         }
-        sd[k] = v;
-    }
-    __syncthreads();
-    for (int k = tid; k < nodes; k += 1024) {
-        const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
-        T vae = T(0), van = T(0);
-        if (interior(g, c)) {
-            const double eP = e[j * NP1 + i], sP = sd[k];
-            if (c + 1 < NN - 1) vae = (T)(eP * e[j * NP1 + i + 1] * inv_h2 * sP * sd[k + 1]);
-            if (g + 1 < NN - 1) van = (T)(eP * e[(j + 1) * NP1 + i] * inv_h2 * sP * sd[k + NN]);
-        }
-        ae[k] = vae;
-        an[k] = van;
+        sd[k] = sdv;
+        tv[k] = (T)tt;
     }
     __syncthreads();
 
@@ -277,7 +428,7 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
         double acc = 0.0;
         for (int k = tid; k < nodes; k += 1024) {
             const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
-            T rvk = T(0);
+            T rk = T(0);
             if (interior(g, c)) {
                 double res = a.f;
                 if (sweep > 0) {
@@ -291,10 +442,10 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
                             e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
                 }
                 acc += res * res;
-                rvk = (T)(sd[k] * res);
+                rk = (T)(sd[k] * res);
             }
-            rv[k] = rvk;
-            pv[k] = rvk;
+            rv[k] = rk;
+            pv[k] = rk;
             xv[k] = T(0);
         }
         const double rr64 = block_sum<NW>(acc, red2);
@@ -308,17 +459,19 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
         bool broke = false;
         while (rr > target) {
             if (total >= a.max_iter) break;
+            for (int k = tid; k < nodes; k += 1024) yv[k] = tv[k] * pv[k];
+            __syncthreads();
             T pq_acc = T(0);
             for (int k = tid; k < nodes; k += 1024) {
                 const int g = k / NN, c = k % NN;
                 T qk = T(0);
                 const T pk = pv[k];
                 if (interior(g, c)) {
-                    const T pE = pv[k + 1];
-                    const T sW = (c > 0) ? ae[k - 1] * pv[k - 1] : T(0);
-                    const T pN = pv[k + NN];
-                    const T sS = (g > 0) ? an[k - NN] * pv[k - NN] : T(0);
-                    qk = pk - ae[k] * pE - sW - an[k] * pN - sS;
+                    const T yE = yv[k + 1];
+                    const T yW = (c > 0) ? yv[k - 1] : T(0);
+                    const T yN = yv[k + NN];
+                    const T yS = (g > 0) ? yv[k - NN] : T(0);
+                    qk = pk - tv[k] * ((yE + yW) + (yN + yS));
                 }
                 qv[k] = qk;
                 pq_acc += pk * qk;
@@ -337,7 +490,6 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
             const T beta = (T)(rrn / rr);
             rr = rrn;
             for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
-            __syncthreads();
             ++total;
         }
         for (int k = tid; k < nodes; k += 1024) {
@@ -406,20 +558,33 @@ __global__ __launch_bounds__(256) void solve1d_kernel(SolveArgs a, int n, int64_
     if (a.iters) a.iters[row] = 0;
 }
 
-template <typename T, int NN, int R>
-static hipError_t run_onchip(int64_t N, const SolveArgs& a, hipStream_t s) {
-    cg_onchip<T, NN, R><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a);
+template <typename T, int NN, int R, bool DST>
+static hipError_t run_onchip(int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
+    cg_onchip<T, NN, R, DST><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, reinterpret_cast<const __bf16*>(S),
+                                                                          lam);
     return hipGetLastError();
+}
+
+bool dst_supported(int n) { return n == 32 || n == 64 || n == 128; }
+
+hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    switch (n) {
+        case 32: return run_onchip<float, 32, 4, true>(N, a, S, lam, s);
+        case 64: return run_onchip<float, 64, 8, true>(N, a, S, lam, s);
+        case 128: return run_onchip<float, 128, 16, true>(N, a, S, lam, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     if (prec == SMC_FP32_REFINE) {
         switch (n) {
-            case 16: return run_onchip<float, 16, 4>(N, a, s);
-            case 32: return run_onchip<float, 32, 4>(N, a, s);
-            case 64: return run_onchip<float, 64, 8>(N, a, s);
-            case 128: return run_onchip<float, 128, 16>(N, a, s);
+            case 16: return run_onchip<float, 16, 4, false>(N, a, nullptr, nullptr, s);
+            case 32: return run_onchip<float, 32, 4, false>(N, a, nullptr, nullptr, s);
+            case 64: return run_onchip<float, 64, 8, false>(N, a, nullptr, nullptr, s);
+            case 128: return run_onchip<float, 128, 16, false>(N, a, nullptr, nullptr, s);
             default:
                 cg_global<float><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, n);
                 return hipGetLastError();
@@ -428,9 +593,9 @@ hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStr
     SolveArgs b = a;
     b.tol_inner = 0.1 * a.tol64;
     switch (n) {
-        case 16: return run_onchip<double, 16, 4>(N, b, s);
-        case 32: return run_onchip<double, 32, 4>(N, b, s);
-        case 64: return run_onchip<double, 64, 8>(N, b, s);
+        case 16: return run_onchip<double, 16, 4, false>(N, b, nullptr, nullptr, s);
+        case 32: return run_onchip<double, 32, 4, false>(N, b, nullptr, nullptr, s);
+        case 64: return run_onchip<double, 64, 8, false>(N, b, nullptr, nullptr, s);
         default:
             cg_global<double><<<dim3((unsigned)N), dim3(1024), 0, s>>>(b, n);
             return hipGetLastError();

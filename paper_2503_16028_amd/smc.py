@@ -18,6 +18,7 @@ SMC_FP64 = 0
 SMC_FP32_REFINE = 1
 FLAG_NOCONV, FLAG_STALL, FLAG_NONFINITE, FLAG_BADWEIGHTS = 1, 2, 4, 8
 PRECISIONS = {"fp64": SMC_FP64, "fp32_refine": SMC_FP32_REFINE}
+PRECOND_AUTO, PRECOND_JACOBI = 0, 1
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
 
@@ -32,7 +33,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("dim", c_i32), ("n_levels", c_i32), ("grid_n", c_i32 * 3), ("kl", c_i32), ("kr", c_i32),
                 ("n_obs", c_i32), ("obs_den", c_i32), ("obs_num", ctypes.POINTER(c_i32)),
                 ("y", ctypes.POINTER(c_dbl)), ("sigma", c_dbl), ("f", c_dbl), ("n_max", c_i64),
-                ("tol64", c_dbl), ("tol_inner", c_dbl), ("max_iter", c_i32), ("max_sweeps", c_i32)]
+                ("tol64", c_dbl), ("tol_inner", c_dbl), ("max_iter", c_i32), ("max_sweeps", c_i32),
+                ("precond", c_i32)]
 
 
 class GMDesc(ctypes.Structure):
@@ -54,6 +56,7 @@ _SIGS = {
     "smc_temper": (c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_resample": (c_i32, [c_i64, c_vp, c_u64, c_vp, c_vp, c_vp]),
     "smc_gather": (c_i32, [c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "smc_precond_apply": (c_i32, [c_vp, c_i32, c_i64, c_vp, c_vp, c_vp]),
     "smc_profile": (c_i32, [c_vp, c_i32]),
     "smc_profile_read": (c_i32, [c_vp, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                  ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
@@ -106,7 +109,8 @@ def _ptr(t, dtype, numel=None, name="tensor", optional=False):
 class Problem:
     """An smc_problem built from a problem definition (dict with the JSON fields)."""
 
-    def __init__(self, d, n_max, grids=None, tol64=1e-10, tol_inner=1e-5, max_iter=None, max_sweeps=8):
+    def __init__(self, d, n_max, grids=None, tol64=1e-10, tol_inner=1e-5, max_iter=None, max_sweeps=8,
+                 precond=PRECOND_AUTO):
         L = lib()
         grids = list(grids if grids is not None else d["grids"])
         self.dim = int(d["dim"])
@@ -132,6 +136,7 @@ class Problem:
         desc.tol_inner = float(tol_inner)
         desc.max_iter = int(max_iter if max_iter is not None else 40 * max(grids))
         desc.max_sweeps = int(max_sweeps)
+        desc.precond = int(precond)
         handle = c_vp()
         _check(L.smc_problem_create(ctypes.byref(desc), ctypes.byref(handle)))
         self.handle = handle
@@ -233,3 +238,9 @@ def smc_profile_read(problem, stream=None):
     vals = [c_i64() for _ in range(4)]
     _check(lib().smc_profile_read(problem.handle, _stream(stream), ctypes.byref(ms), *[ctypes.byref(v) for v in vals]))
     return dict(ms=ms.value, launches=vals[0].value, iters=vals[1].value, sweeps=vals[2].value, solves=vals[3].value)
+
+
+def smc_precond_apply(problem, level, N, r, z, stream=None):
+    n = problem.grids[level]
+    _check(lib().smc_precond_apply(problem.handle, int(level), N, _ptr(r, torch.float32, N * n * n, "r"),
+                                   _ptr(z, torch.float32, N * n * n, "z"), _stream(stream)))

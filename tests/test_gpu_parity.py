@@ -120,13 +120,58 @@ def test_forward_fp32_refine(name, grid, N):
     xi = inputs.particles(N, op.K, 3)
     G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
     phi = torch.empty(N, dtype=torch.float64, device=DEV)
-    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP32_REFINE, G)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP32_REFINE, G, it)
     smc.smc_potential(p, N, G, phi)
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
     assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    if grid in (32, 64, 128):                           # fast-Poisson preconditioner: grid-independent
+        assert (it.cpu().numpy() < 60).all(), it
     ref_phi = potential(ref, op.y, op.sigma)
     assert np.abs(phi.cpu().numpy() / ref_phi - 1).max() <= 1e-4
+
+
+@pytest.mark.parametrize("grid", [32, 64, 128])
+def test_fast_poisson_preconditioner(grid):
+    """z = L^{-1} r up to a constant, against the same formula in FP64 (bf16 transforms: 2e-2)."""
+    from paper_2503_16028_amd import smc
+    banner("fast-Poisson preconditioner", grid)
+    d, op = load("c5" if grid != 32 else "t2")
+    p = gpu_problem(d, 3, grids=[grid])
+    n = grid
+    r = inputs.particles(3, n * n, 9).reshape(3, n, n)
+    r[:, n - 1, :] = 0.0
+    r[:, :, n - 1] = 0.0
+    z = torch.empty(3, n, n, dtype=torch.float32, device=DEV)
+    smc.smc_precond_apply(p, 0, 3, torch.tensor(r, dtype=torch.float32, device=DEV).contiguous(), z)
+    torch.cuda.synchronize()
+    a = np.arange(1, n)
+    S = np.sqrt(2.0 / n) * np.sin(np.pi * np.outer(a, a) / n)
+    lam = np.sin(np.pi * a / (2 * n)) ** 2
+    got = z.cpu().numpy()
+    for k in range(3):
+        ref = S @ ((S @ r[k, :n - 1, :n - 1] @ S) / (lam[:, None] + lam[None, :])) @ S
+        assert np.abs(got[k, :n - 1, :n - 1] - ref).max() <= 2e-2 * np.abs(ref).max()
+        assert np.abs(got[k, n - 1, :]).max() == 0 and np.abs(got[k, :, n - 1]).max() == 0
+
+
+@pytest.mark.parametrize("name,grid,N", [("t2", 32, 9), ("c2", 64, 5), ("c3", 128, 4)])
+def test_forward_fp32_jacobi_only(name, grid, N):
+    """The Jacobi-preconditioned FP32 path (the fast-Poisson one is the default on these grids)."""
+    from paper_2503_16028_amd import smc
+    banner("forward fp32+refine jacobi", name, grid, N)
+    d, op = load(name)
+    p = gpu_problem(d, N, grids=[grid], tol64=1e-10, tol_inner=1e-5, max_iter=80 * grid,
+                    precond=smc.PRECOND_JACOBI)
+    xi = inputs.particles(N, op.K, 8)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP32_REFINE, G, it)
+    torch.cuda.synchronize()
+    ref = oracle_G(op, xi, grid)
+    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    assert (it.cpu().numpy() > 3 * grid).all()          # Jacobi needs O(n) iterations per decade
 
 
 @pytest.mark.parametrize("name,grid", [("t1", 16), ("t1", 64), ("c1", 64)])
