@@ -19,9 +19,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PROBLEM = os.path.join(ROOT, "tests", "golden", "problem_c3.json")
 N, M, N_MOVES, GRID = 4096, 8, 20, 128
-FLOPS_PER_UNKNOWN_ITER = 20     # one scaled-CG iteration per interior unknown
+FLOPS_PER_UNKNOWN_ITER = 18     # one scaled-CG iteration per interior unknown, product-form stencil
 FLOPS_PER_UNKNOWN_SWEEP = 16    # one FP64 residual evaluation per interior unknown
 FP32_VECTOR_PEAK = 157.3e12     # MI355X published FP32 vector peak
+BF16_MFMA_PEAK = 2.5e15         # MI355X published dense bf16 matrix peak
 
 
 def cpu_baseline(d, sample_per_worker=40):
@@ -68,6 +69,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--moves", type=int, default=N_MOVES, help="moves per stage (profiling runs use fewer)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also copy 256 MiB device-to-device, to calibrate memory-traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs the move stage on one GPU only (--gpus %d requested); the multi-GPU sharding "
@@ -121,13 +125,22 @@ def main():
         smc.smc_profile(p, 0)
         return timed, solve, s
 
-    t32, prof32, s32 = stage_loop(smc.SMC_FP32_REFINE, args.steps, args.warmup, N_MOVES)
-    moves = N * N_MOVES * args.steps
+    if args.copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    t32, prof32, s32 = stage_loop(smc.SMC_FP32_REFINE, args.steps, args.warmup, args.moves)
+    moves = N * args.moves * args.steps
     value = moves / t32
     launches = max(1, prof32["launches"])
     kernel_ms = prof32["ms"] / launches
-    flops = unknowns * (FLOPS_PER_UNKNOWN_ITER * prof32["iters"] + FLOPS_PER_UNKNOWN_SWEEP * prof32["sweeps"])
-    achieved = flops / (prof32["ms"] * 1e-3)
+    # algorithmic work of the solve launches: four n^3 sine-transform products (2 FLOP per
+    # multiply-add) per preconditioner application on the matrix cores, plus the CG vector work
+    mfma_flops = 8.0 * GRID ** 3 * prof32["precond_apps"]
+    valu_flops = unknowns * (FLOPS_PER_UNKNOWN_ITER * prof32["iters"] + FLOPS_PER_UNKNOWN_SWEEP * prof32["sweeps"])
+    achieved = mfma_flops / (prof32["ms"] * 1e-3)
     variants = {}
     if not args.no_variants:
         t64, prof64, _ = stage_loop(smc.SMC_FP64, 1, 0, 4)
@@ -173,12 +186,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D Darcy 128x128, N=4096 particles, 8-component GM-pCN over 64 active modes, "
                                "20 moves per tempering stage, 10 mirrored observations",
-                   "grid": GRID, "particles": N, "mixture": M, "moves_per_stage": N_MOVES,
-                   "solver": "Jacobi-scaled CG in FP32 inside FP64 residual refinement, tol 1e-10"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-                     "kernel": "cg_onchip<float,128,16>", "kernel_ms_per_launch": kernel_ms,
+                   "grid": GRID, "particles": N, "mixture": M, "moves_per_stage": args.moves,
+                   "solver": "Jacobi-scaled CG in FP32, fast-Poisson (bf16 MFMA sine transform) preconditioner, "
+                             "inside FP64 residual refinement to 1e-10"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK, "traffic": None,
+                     "kernel": "cg_onchip<float,128,16,fast-Poisson>", "kernel_ms_per_launch": kernel_ms,
+                     "valu_tflops": valu_flops / (prof32["ms"] * 1e-3) / 1e12,
                      "cg_iters_per_solve": prof32["iters"] / max(1, prof32["solves"]),
+                     "precond_apps_per_solve": prof32["precond_apps"] / max(1, prof32["solves"]),
                      "sweeps_per_solve": prof32["sweeps"] / max(1, prof32["solves"])},
         "cpu_baseline": cpu,
         "variants": variants,

@@ -182,12 +182,13 @@ int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, f
 /* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by
  * smc_forward_batch and smc_gmpcn_move on p is then bracketed by two HIP events recorded on
  * the call's stream, and the solve kernels add their conjugate-gradient iterations, FP64
- * residual sweeps and solve count to a device counter.  smc_profile(p, 0) stops.
- * smc_profile_read synchronises `stream` and returns the summed kernel time (ms), the number
- * of timed launches, and the iteration, sweep and solve totals (host outputs, any may be NULL). */
+ * residual sweeps, solve count and fast-Poisson preconditioner applications to device
+ * counters.  smc_profile(p, 0) stops.  smc_profile_read synchronises `stream` and returns the
+ * summed kernel time (ms), the number of timed launches and those totals (host outputs, any
+ * may be NULL). */
 int smc_profile(smc_problem p, int32_t enable);
 int smc_profile_read(smc_problem p, smc_stream stream, double* ms, int64_t* launches, int64_t* iters,
-                     int64_t* sweeps, int64_t* solves);
+                     int64_t* sweeps, int64_t* solves, int64_t* precond_apps);
 
 #ifdef __cplusplus
 }

@@ -203,8 +203,8 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     ck(hipMalloc((void**)&P.ws_G, sizeof(double) * Nm * P.n_obs));
     ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
-    ck(hipMalloc((void**)&P.stats, 3 * sizeof(unsigned long long)));
-    ck(hipMemset(P.stats, 0, 3 * sizeof(unsigned long long)));
+    ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
+    ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
     ck(hipMemset(P.flags, 0, sizeof(int32_t)));
     ck(hipDeviceSynchronize());
     if (e != hipSuccess) {
@@ -239,7 +239,7 @@ extern "C" int smc_profile(smc_problem p, int32_t enable) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
     if (enable) {
         HIPCHK(hipDeviceSynchronize());
-        HIPCHK(hipMemset(p->P.stats, 0, 3 * sizeof(unsigned long long)));
+        HIPCHK(hipMemset(p->P.stats, 0, 4 * sizeof(unsigned long long)));
         HIPCHK(hipDeviceSynchronize());
         p->pool.used = 0;
     }
@@ -248,7 +248,7 @@ extern "C" int smc_profile(smc_problem p, int32_t enable) {
 }
 
 extern "C" int smc_profile_read(smc_problem p, smc_stream stream, double* ms, int64_t* launches, int64_t* iters,
-                                int64_t* sweeps, int64_t* solves) {
+                                int64_t* sweeps, int64_t* solves, int64_t* precond_apps) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     double tot = 0.0;
@@ -257,13 +257,14 @@ extern "C" int smc_profile_read(smc_problem p, smc_stream stream, double* ms, in
         HIPCHK(hipEventElapsedTime(&t, p->pool.ev[k], p->pool.ev[k + 1]));
         tot += t;
     }
-    unsigned long long st[3];
+    unsigned long long st[4];
     HIPCHK(hipMemcpy(st, p->P.stats, sizeof(st), hipMemcpyDeviceToHost));
     if (ms) *ms = tot;
     if (launches) *launches = (int64_t)(p->pool.used / 2);
     if (iters) *iters = (int64_t)st[0];
     if (sweeps) *sweeps = (int64_t)st[1];
     if (solves) *solves = (int64_t)st[2];
+    if (precond_apps) *precond_apps = (int64_t)st[3];
     return SMC_OK;
 }
 

@@ -45,7 +45,7 @@ struct Problem {
     double* ws_G = nullptr;      // [n_max][n_obs]
     int32_t* ws_iters = nullptr; // [n_max]
     int32_t* flags = nullptr;    // device status word
-    unsigned long long* stats = nullptr;  // [3] iterations, sweeps, solves (while profiling)
+    unsigned long long* stats = nullptr;  // [4] iterations, sweeps, solves, preconditioner applications
     bool profiling = false;
     void* events = nullptr;      // host-side event list (api.hip)
     int64_t e_stride = 0, x_stride = 0, vec_stride = 0;
@@ -130,7 +130,7 @@ struct SolveArgs {
     double* phi;         // [N] or null
     int32_t* iters;      // [N] or null
     int32_t* flags;
-    unsigned long long* stats;   // [3] iterations, sweeps, solves; null when not profiling
+    unsigned long long* stats;   // [4] iterations, sweeps, solves, preconditioner applications; or null
 };
 
 hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_lam, const double* basis, int n,

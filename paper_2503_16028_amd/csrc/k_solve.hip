@@ -59,7 +59,7 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
     constexpr int LD = DS::LD, LDZ = DS::LDZ, KS = DS::KS, TPW = DS::TPW, NB = DS::NB;
     __bf16* bufA = reinterpret_cast<__bf16*>(smem);   // R^T, later T2^T
     __bf16* bufB = bufA + NN * LD;                    // T1, later T3
-    float* ZT = reinterpret_cast<float*>(bufB + NN * LD);
+    float* Z = reinterpret_cast<float*>(bufB + NN * LD);   // Z[g][c]: lanes of a row read consecutive words
     const int lr = lane & 15, lk = lane >> 4;
     const int sb = wave % NB, wq = wave / NB;
     bf8 sfrag[KS];   // rows sb*16.. of S (symmetric: also columns sb*16.. as a B operand)
@@ -104,7 +104,7 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int k = rb * 16 + 4 * lk + v;
-            bufA[(sb * 16 + lr) * LD + k] = (__bf16)(acc[v] / (lamtab[k] + lam_col));
+            bufA[(sb * 16 + lr) * LD + k] = (__bf16)(acc[v] * __builtin_amdgcn_rcpf(lamtab[k] + lam_col));
         }
     }
     __syncthreads();
@@ -120,14 +120,14 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
     }
     __syncthreads();
 #pragma unroll 1
-    for (int tt = 0; tt < TPW; ++tt) {   // ZT[c][g] = sum_l T3[g][l] S[l][c]
+    for (int tt = 0; tt < TPW; ++tt) {   // Z[g][c] = sum_l T3[g][l] S[l][c]
         const int rb = wq * TPW + tt;
         f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
             acc = mfma_bf16(*reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk), sfrag[ks], acc);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ZT[(sb * 16 + lr) * LDZ + rb * 16 + 4 * lk + v] = acc[v];
+        for (int v = 0; v < 4; ++v) Z[(rb * 16 + 4 * lk + v) * LDZ + sb * 16 + lr] = acc[v];
     }
     __syncthreads();
 }
@@ -146,9 +146,9 @@ __global__ __launch_bounds__(NN * NN / R) void dst_apply_kernel(const float* __r
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = rin[base + (b * R + k) * NN + c];
     dst_apply<float, NN, R, NW>(r, smem, Stab, lamtab, c, b, tid >> 6, tid & 63);
-    const float* ZT = reinterpret_cast<const float*>(smem + 2 * NN * DstShape<NN, NW>::LD * 2);
+    const float* Z = reinterpret_cast<const float*>(smem + 2 * NN * DstShape<NN, NW>::LD * 2);
 #pragma unroll
-    for (int k = 0; k < R; ++k) zout[base + (b * R + k) * NN + c] = ZT[c * DstShape<NN, NW>::LDZ + b * R + k];
+    for (int k = 0; k < R; ++k) zout[base + (b * R + k) * NN + c] = Z[(b * R + k) * DstShape<NN, NW>::LDZ + c];
 }
 
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
@@ -196,32 +196,42 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
     }
     // ---- setup: D^{-1/2} (FP64, workspace) and t (registers); work outside the CG loop runs
     // as plain loops that stage through the thread's own LDS slots
+    {
+        // column i of e, rows j-1, j, j+1 carried along the strip (j = g + 1)
+        double eS = e[(b * R) * NP1 + i], eC = e[(b * R + 1) * NP1 + i];
 #pragma unroll 1
-    for (int r = 0; r < R; ++r) {
-        const int g = b * R + r, j = g + 1;
-        double sdv = 1.0, tv = 0.0;
-        if (c < NN - 1 && g < NN - 1) {
-            const double eP = e[j * NP1 + i];
-            const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i];
-            sdv = h / sqrt(eP * S);
-            tv = sqrt(eP / S);
+        for (int r = 0; r < R; ++r) {
+            const int g = b * R + r, j = g + 1;
+            const double eN = (j + 1 <= NN) ? e[(j + 1) * NP1 + i] : 0.0;
+            double sdv = 1.0, tv = 0.0;
+            if (c < NN - 1 && g < NN - 1) {
+                const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + eN + eS;
+                sdv = h / sqrt(eC * S);
+                tv = sqrt(eC / S);
+            }
+            sd[g * NN + c] = sdv;
+            tb[NN + 1 + r * NN] = (T)tv;
+            eS = eC;
+            eC = eN;
         }
-        sd[g * NN + c] = sdv;
-        tb[NN + 1 + r * NN] = (T)tv;
     }
     T t[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) t[r] = tb[NN + 1 + r * NN];
     __syncthreads();
 
-    // z = L^{-1} r into ZT[c][g] (LDS), with the barriers of the four products
+    // z = L^{-1} r into Z[g][c] (LDS), with the barriers of the four products
+    int napp = 0;   // preconditioner applications (same in every thread)
     auto precondition = [&](const T (&rin)[R]) __attribute__((always_inline)) {
-        if constexpr (DST) dst_apply<T, NN, R, NW>(rin, smem, Stab, lamtab, c, b, wave, lane);
+        if constexpr (DST) {
+            dst_apply<T, NN, R, NW>(rin, smem, Stab, lamtab, c, b, wave, lane);
+            ++napp;
+        }
     };
     auto zval = [&](int r) __attribute__((always_inline)) -> T {
         if constexpr (DST) {
-            const float* ZT = reinterpret_cast<const float*>(smem + 2 * NN * DS::LD * 2);
-            return (T)ZT[c * DS::LDZ + b * R + r];
+            const float* Z = reinterpret_cast<const float*>(smem + 2 * NN * DS::LD * 2);
+            return (T)Z[(b * R + r) * DS::LDZ + c];
         } else {
             return T(0);
         }
@@ -235,26 +245,44 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
     for (int sweep = 0;; ++sweep) {
         sweeps = sweep;
         double acc = 0.0;
+        if (sweep == 0) {
 #pragma unroll 1
-        for (int r = 0; r < R; ++r) {
-            const int g = b * R + r, j = g + 1;
-            T out = T(0);
-            if (c < NN - 1 && g < NN - 1) {
-                double res = a.f;
-                if (sweep > 0) {
-                    const double xP = x64[g * NN + c];
+            for (int r = 0; r < R; ++r) {
+                const int g = b * R + r;
+                T out = T(0);
+                if (c < NN - 1 && g < NN - 1) {
+                    acc += a.f * a.f;
+                    out = (T)(sd[g * NN + c] * a.f);
+                }
+                tb[NN + 1 + r * NN] = out;
+            }
+        } else {
+            // r = f - A x in FP64; column i of e and x carried along the strip
+            const int g0 = b * R;
+            double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
+            double xS = (g0 > 0 && c < NN - 1) ? x64[(g0 - 1) * NN + c] : 0.0;
+            double xC = (g0 < NN - 1 && c < NN - 1) ? x64[g0 * NN + c] : 0.0;
+#pragma unroll 1
+            for (int r = 0; r < R; ++r) {
+                const int g = g0 + r, j = g + 1;
+                const double eN = (j + 1 <= NN) ? e[(j + 1) * NP1 + i] : 0.0;
+                const double xN = (g + 1 < NN - 1 && c < NN - 1) ? x64[(g + 1) * NN + c] : 0.0;
+                T out = T(0);
+                if (c < NN - 1 && g < NN - 1) {
                     const double xE = (c + 1 < NN - 1) ? x64[g * NN + c + 1] : 0.0;
                     const double xW = (c > 0) ? x64[g * NN + c - 1] : 0.0;
-                    const double xN = (g + 1 < NN - 1) ? x64[(g + 1) * NN + c] : 0.0;
-                    const double xS = (g > 0) ? x64[(g - 1) * NN + c] : 0.0;
-                    res -= e[j * NP1 + i] * inv_h2 *
-                           (e[j * NP1 + i + 1] * (xP - xE) + e[j * NP1 + i - 1] * (xP - xW) +
-                            e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
+                    const double res = a.f - eC * inv_h2 *
+                                                 (e[j * NP1 + i + 1] * (xC - xE) + e[j * NP1 + i - 1] * (xC - xW) +
+                                                  eN * (xC - xN) + eS * (xC - xS));
+                    acc += res * res;
+                    out = (T)(sd[g * NN + c] * res);
                 }
-                acc += res * res;
-                out = (T)(sd[g * NN + c] * res);
+                tb[NN + 1 + r * NN] = out;
+                eS = eC;
+                eC = eN;
+                xS = xC;
+                xC = xN;
             }
-            tb[NN + 1 + r * NN] = out;
         }
         const double rr64 = block_sum<NW>(acc, red2);
         if (sqrt(rr64) <= a.tol64 * fnorm) { ok = true; break; }
@@ -377,6 +405,7 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
                 atomicAdd(&a.stats[0], (unsigned long long)total);
                 atomicAdd(&a.stats[1], (unsigned long long)(sweeps + 1));
                 atomicAdd(&a.stats[2], 1ull);
+                atomicAdd(&a.stats[3], (unsigned long long)napp);
             }
         }
     }

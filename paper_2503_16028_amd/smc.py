@@ -59,7 +59,7 @@ _SIGS = {
     "smc_precond_apply": (c_i32, [c_vp, c_i32, c_i64, c_vp, c_vp, c_vp]),
     "smc_profile": (c_i32, [c_vp, c_i32]),
     "smc_profile_read": (c_i32, [c_vp, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
-                                 ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+                                 ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
 }
 EXPORTED = sorted(_SIGS)
 
@@ -233,11 +233,12 @@ def smc_profile(problem, enable):
 
 
 def smc_profile_read(problem, stream=None):
-    """dict(ms, launches, iters, sweeps, solves) for the solve launches since smc_profile(p, 1)."""
+    """dict(ms, launches, iters, sweeps, solves, precond_apps) for the solve launches since smc_profile(p, 1)."""
     ms = c_dbl()
-    vals = [c_i64() for _ in range(4)]
+    vals = [c_i64() for _ in range(5)]
     _check(lib().smc_profile_read(problem.handle, _stream(stream), ctypes.byref(ms), *[ctypes.byref(v) for v in vals]))
-    return dict(ms=ms.value, launches=vals[0].value, iters=vals[1].value, sweeps=vals[2].value, solves=vals[3].value)
+    return dict(ms=ms.value, launches=vals[0].value, iters=vals[1].value, sweeps=vals[2].value, solves=vals[3].value,
+                precond_apps=vals[4].value)
 
 
 def smc_precond_apply(problem, level, N, r, z, stream=None):
