@@ -149,6 +149,38 @@ int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, doub
                    int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level,
                    int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
 
+/* Forward solve that keeps its FP64 solution (the forward state of the adjoint gradient), on
+ * grid 0 of a 2D problem: as smc_forward_batch, and w[N][n][n] out with element [g][c] the
+ * solution at the node ((c+1)/n, (g+1)/n); index n-1 is boundary padding and holds 0.  The
+ * caller owns w; passing it to smc_value_and_grad later skips the forward solve there.
+ * G may be NULL. */
+int smc_forward_state(smc_problem p, int64_t N, const double* xi, int32_t prec, double* G, double* w,
+                      int32_t* iters, smc_stream stream);
+
+/* Potential and its gradient in whitened coordinates, g = dPhi/dxi, by one adjoint solve per
+ * particle (the extra PDE solve that Sec. 2.4 counts for gradient-informed moves), 2D only:
+ *   A(u) w = f,  A(u) lam = P^T (P w - y) / sigma^2  (A is symmetric),
+ *   dPhi/du_P = -(1/2) sum over the faces (P,Q) at node P of a_PQ (lam_P - lam_Q)(w_P - w_Q) / h^2,
+ *   g = sqrt(lambda) (B^T dPhi/du B)  (the transpose of the synthesis).
+ *   w     [N][n][n] forward states from smc_forward_state for the same xi and grid, or NULL to
+ *         solve the forward problems here (recomputation from the checkpoint xi)
+ *   phi   [N] out (may be NULL); grad [N][K] out, NaN rows where a solve did not converge
+ *   iters [N] out (may be NULL): total conjugate-gradient iterations, -1 if a solve failed.
+ * Both solves run at precision prec to the problem's FP64 tolerance. */
+int smc_value_and_grad(smc_problem p, int64_t N, const double* xi, int32_t prec, const double* w,
+                       double* phi, double* grad, int32_t* iters, smc_stream stream);
+
+/* n_moves pCN-Langevin steps (named in Sec. 2.4; the Crank-Nicolson step of App. B with the
+ * tempered potential's drift explicit) targeting exp(-tau Phi) mu_0 on grid 0 of a 2D problem:
+ *   v = gamma xi - (1 - gamma) tau g(xi) + beta z,  gamma = sqrt(1 - beta^2),  g = dPhi/dxi,
+ *   accept iff log U_acc < min{0, log of the ratio of target times proposal densities}.
+ * Each proposal costs a forward and an adjoint solve.  Random numbers as in smc_gmpcn_move.
+ *   xi [N][K], phi [N], grad [N][K] in/out (phi and grad must belong to xi, e.g. from
+ *   smc_value_and_grad); n_acc [N] out.  A proposal with a failed solve is rejected. */
+int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, int32_t n_moves, uint64_t seed,
+                  uint64_t ctr, int32_t prec, double* xi, double* phi, double* grad, int32_t* n_acc,
+                  smc_stream stream);
+
 /* Re-weighting and next temperature (Alg. 1; App. C): with tau = *tau_in (device scalar),
  * choose h in (0, 1 - tau] by 64 bisection steps keeping ESS(h) >= ess_frac * N, where
  * ESS = 1 / sum W^2 and W_n ∝ exp(-h Phi_n); take h = 1 - tau when that already passes.
@@ -180,7 +212,8 @@ int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
 int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z, smc_stream stream);
 
 /* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by
- * smc_forward_batch and smc_gmpcn_move on p is then bracketed by two HIP events recorded on
+ * smc_forward_batch, smc_forward_state, smc_value_and_grad, smc_gmpcn_move and smc_pcnl_move on p
+ * is then bracketed by two HIP events recorded on
  * the call's stream, and the solve kernels add their conjugate-gradient iterations, FP64
  * residual sweeps, solve count and fast-Poisson preconditioner applications to device
  * counters.  smc_profile(p, 0) stops.  smc_profile_read synchronises `stream` and returns the

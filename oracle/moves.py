@@ -153,13 +153,14 @@ def log_accept_pcnl(beta, tau, xi, phi_xi, g_xi, v, phi_v, g_v):
     return min(0.0, log_ratio_pcnl(beta, tau, xi, phi_xi, g_xi, v, phi_v, g_v))
 
 
-def pcnl_moves(beta, tau, xi, phi, grad, n_moves, seed, ctr, value_and_grad):
-    """pCN-Langevin steps; value_and_grad(xi) -> (Phi, grad Phi)."""
+def pcnl_moves(beta, tau, xi, phi, grad, n_moves, seed, ctr, value_and_grad, ids=None):
+    """pCN-Langevin steps; value_and_grad(xi) -> (Phi, grad Phi).  Particle ids (the random
+    streams) are row numbers unless `ids` gives them."""
     xi = np.array(xi, dtype=np.float64, copy=True)
     phi = np.array(phi, dtype=np.float64, copy=True)
     grad = np.array(grad, dtype=np.float64, copy=True)
     N, K = xi.shape
-    ids = np.arange(N)
+    ids = np.arange(N) if ids is None else np.asarray(ids)
     n_acc = np.zeros(N, dtype=np.int64)
     for mv in range(n_moves):
         c = ctr + mv

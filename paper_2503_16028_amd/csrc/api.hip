@@ -54,7 +54,8 @@ static void free_problem(Problem& P) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     for (int l = 0; l < MAX_LEVELS; ++l) { f(P.lv[l].basis); f(P.lv[l].obs_node); f(P.lv[l].dst_S); f(P.lv[l].dst_lam); }
     f(P.sqrt_lam); f(P.active); f(P.slot); f(P.y);
-    f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_sd); f(P.ws_vec);
+    f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_lam); f(P.ws_gnew); f(P.ws_sd);
+    f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.flags); f(P.stats);
 }
 
@@ -199,6 +200,10 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     ck(hipMalloc((void**)&P.ws_e, sizeof(double) * Nm * P.e_stride));
     ck(hipMalloc((void**)&P.ws_x64, sizeof(double) * Nm * P.x_stride));
     ck(hipMalloc((void**)&P.ws_sd, sizeof(double) * Nm * P.x_stride));
+    if (P.dim == 2) {
+        ck(hipMalloc((void**)&P.ws_lam, sizeof(double) * Nm * P.x_stride));
+        ck(hipMalloc((void**)&P.ws_gnew, sizeof(double) * Nm * K));
+    }
     if (P.dim == 2 && P.n_big >= 128) ck(hipMalloc(&P.ws_vec, sizeof(double) * Nm * P.vec_stride));
     ck(hipMalloc((void**)&P.ws_G, sizeof(double) * Nm * P.n_obs));
     ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
@@ -332,7 +337,11 @@ static SolveArgs solve_args(const Problem& P, int level) {
     a.vec = P.ws_vec;
     a.e_stride = P.e_stride;
     a.x_stride = P.x_stride;
+    a.sd_stride = P.x_stride;
     a.vec_stride = P.vec_stride;
+    a.lam = nullptr;
+    a.lam_stride = P.x_stride;
+    a.fwd_given = 0;
     a.row0 = 0;
     a.obs = P.lv[level].obs_node;
     a.n_obs = P.n_obs;
@@ -348,19 +357,35 @@ static SolveArgs solve_args(const Problem& P, int level) {
     return a;
 }
 
-// Synthesis then solve for N particles of one grid; outputs per particle (any may be NULL).
-static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, double* G,
-                          double* phi, int32_t* iters, hipStream_t s) {
+// Outputs and options of one batch of forward (and adjoint) solves; every pointer may be NULL.
+struct Solve {
+    double* G = nullptr;
+    double* phi = nullptr;
+    int32_t* iters = nullptr;
+    double* w = nullptr;          // caller's forward-state buffer [N][n*n] (else the workspace)
+    bool w_given = false;         // w already holds the forward solutions: solve the adjoint only
+    bool adjoint = false;         // also solve A lam = P^T (P w - y) / sigma^2 into the workspace
+};
+
+// Synthesis then solve for N particles of one grid.
+static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, const Solve& o,
+                          hipStream_t s) {
     const Problem& P = ps->P;
     hipError_t e = synth(P, level, N, xi, P.ws_e, P.e_stride, true, s);
     if (e != hipSuccess) return e;
+    const Level& L = P.lv[level];
     SolveArgs a = solve_args(P, level);
-    a.G = G;
-    a.phi = phi;
-    a.iters = iters;
+    a.G = o.G;
+    a.phi = o.phi;
+    a.iters = o.iters;
+    if (o.w) {
+        a.x64 = o.w;
+        a.x_stride = P.dim == 2 ? (int64_t)L.n * L.n : L.n + 1;
+    }
+    a.fwd_given = o.w_given ? 1 : 0;
+    a.lam = o.adjoint ? P.ws_lam : nullptr;
     a.stats = P.profiling ? P.stats : nullptr;
     if (P.profiling && (e = record(ps->pool, s)) != hipSuccess) return e;
-    const Level& L = P.lv[level];
     if (P.dim == 1)
         e = launch_solve1d(L.n, N, a, s);
     else if (prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S)
@@ -372,6 +397,14 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     return e;
 }
 
+// Gradient of the N particles' potentials after forward(..., adjoint = true).
+static hipError_t gradient(const Problem& P, int level, int64_t N, const double* w, int64_t w_stride,
+                           const int32_t* iters, double* grad, hipStream_t s) {
+    const Level& L = P.lv[level];
+    return launch_gradsynth2d(P.ws_e, P.e_stride, w, w_stride, P.ws_lam, P.x_stride, iters, P.sqrt_lam, L.basis, L.n,
+                              P.kl, P.K, grad, N, s);
+}
+
 extern "C" int smc_forward_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level,
                                  int32_t prec, double* G, int32_t* iters, smc_stream stream) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
@@ -379,7 +412,48 @@ extern "C" int smc_forward_batch(smc_problem p, int64_t N, const double* xi, con
     if (N > 0 && (!xi || !G)) return fail(SMC_E_INVAL, "xi and G must not be NULL");
     if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
     if (level) return fail(SMC_E_INVAL, "per-particle level maps are not supported by this call; pass NULL");
-    HIPCHK(forward(p, 0, prec, N, xi, G, nullptr, iters, (hipStream_t)stream));
+    Solve o;
+    o.G = G;
+    o.iters = iters;
+    HIPCHK(forward(p, 0, prec, N, xi, o, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_forward_state(smc_problem p, int64_t N, const double* xi, int32_t prec, double* G, double* w,
+                                 int32_t* iters, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (p->P.dim != 2) return fail(SMC_E_INVAL, "forward states are kept for the 2D problem only");
+    if (int r = check_n(p->P, N)) return r;
+    if (N > 0 && (!xi || !w)) return fail(SMC_E_INVAL, "xi and w must not be NULL");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    Solve o;
+    o.G = G;
+    o.iters = iters;
+    o.w = w;
+    HIPCHK(forward(p, 0, prec, N, xi, o, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" int smc_value_and_grad(smc_problem p, int64_t N, const double* xi, int32_t prec, const double* w,
+                                  double* phi, double* grad, int32_t* iters, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (P.dim != 2) return fail(SMC_E_INVAL, "the adjoint gradient is implemented for the 2D problem");
+    if (int r = check_n(P, N)) return r;
+    if (N > 0 && (!xi || !grad)) return fail(SMC_E_INVAL, "xi and grad must not be NULL");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    hipStream_t s = (hipStream_t)stream;
+    Solve o;
+    o.phi = phi;
+    o.iters = iters ? iters : P.ws_iters;
+    o.adjoint = true;
+    if (w) {
+        o.w = const_cast<double*>(w);   // read only: the forward pass is skipped
+        o.w_given = true;
+    }
+    HIPCHK(forward(p, 0, prec, N, xi, o, s));
+    const int n = P.lv[0].n;
+    HIPCHK(gradient(P, 0, N, w ? w : P.ws_x64, w ? (int64_t)n * n : P.x_stride, o.iters, grad, s));
     return SMC_OK;
 }
 
@@ -414,8 +488,41 @@ extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double
         const uint64_t c = ctr + (uint64_t)m;
         HIPCHK(launch_propose(N, P.K, P.kr, gm->M, P.active, P.slot, gm->logw, gm->mean, gm->scale, beta, seed, c,
                               xi, P.ws_v, P.ws_logr, s));
-        HIPCHK(forward(p, 0, prec, N, P.ws_v, nullptr, P.ws_phinew, P.ws_iters, s));
+        Solve o;
+        o.phi = P.ws_phinew;
+        o.iters = P.ws_iters;
+        HIPCHK(forward(p, 0, prec, N, P.ws_v, o, s));
         HIPCHK(launch_accept(N, P.K, tau, seed, c, P.ws_v, P.ws_logr, P.ws_phinew, xi, phi, n_acc, s));
+    }
+    return SMC_OK;
+}
+
+extern "C" int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, int32_t n_moves, uint64_t seed,
+                             uint64_t ctr, int32_t prec, double* xi, double* phi, double* grad, int32_t* n_acc,
+                             smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (P.dim != 2) return fail(SMC_E_INVAL, "the pCN-Langevin move needs the 2D adjoint gradient");
+    if (int r = check_n(P, N)) return r;
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SMC_E_INVAL, "beta must be in (0, 1]");
+    if (!(tau >= 0.0 && tau <= 1.0)) return fail(SMC_E_INVAL, "tau must be in [0, 1]");
+    if (n_moves < 0) return fail(SMC_E_INVAL, "n_moves must be >= 0");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (N > 0 && (!xi || !phi || !grad || !n_acc)) return fail(SMC_E_INVAL, "xi, phi, grad and n_acc must not be NULL");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_fill_i32(n_acc, N, 0, s));
+    for (int m = 0; m < n_moves; ++m) {
+        const uint64_t c = ctr + (uint64_t)m;
+        HIPCHK(launch_pcnl_propose(N, P.K, beta, tau, seed, c, xi, grad, P.ws_v, s));
+        Solve o;
+        o.phi = P.ws_phinew;
+        o.iters = P.ws_iters;
+        o.adjoint = true;
+        HIPCHK(forward(p, 0, prec, N, P.ws_v, o, s));
+        HIPCHK(gradient(P, 0, N, P.ws_x64, P.x_stride, P.ws_iters, P.ws_gnew, s));
+        HIPCHK(launch_pcnl_accept(N, P.K, beta, tau, seed, c, P.ws_v, P.ws_gnew, P.ws_phinew, P.ws_iters, xi, grad,
+                                  phi, n_acc, s));
     }
     return SMC_OK;
 }

@@ -40,6 +40,8 @@ struct Problem {
     double* ws_phinew = nullptr; // [n_max]       potential of the proposal
     double* ws_e = nullptr;      // [n_max][(n_big+1)^dim]  exp(u/2) at the nodes
     double* ws_x64 = nullptr;    // [n_max][n_big^dim]      FP64 solution
+    double* ws_lam = nullptr;    // [n_max][n_big^2]        FP64 adjoint solution (2D)
+    double* ws_gnew = nullptr;   // [n_max][K]              gradient at the proposal (2D)
     double* ws_sd = nullptr;     // [n_max][n_big^2]        D^{-1/2} of the Jacobi scaling
     void* ws_vec = nullptr;      // [n_max][6][n_big^2] doubles: vectors of the global-memory solver
     double* ws_G = nullptr;      // [n_max][n_obs]
@@ -118,7 +120,10 @@ struct SolveArgs {
     double* x64;         // FP64 solution, row stride x_stride
     double* sd;          // D^{-1/2}, row stride x_stride
     void* vec;           // global-solver vectors, row stride vec_stride (doubles)
-    int64_t e_stride, x_stride, vec_stride;
+    int64_t e_stride, x_stride, sd_stride, vec_stride;
+    double* lam;         // adjoint solution [N][lam_stride] (interior layout as x64), or null: no adjoint
+    int64_t lam_stride;
+    int fwd_given;       // x64 already holds the forward solution: only the adjoint problem is solved
     int64_t row0;        // first particle row
     const int32_t* obs;  // [n_obs] nodal flat index
     int n_obs;
@@ -137,6 +142,14 @@ hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_la
                           double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
 hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, const double* basis, int n, double* out,
                           int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
+hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w, int64_t w_stride,
+                              const double* lam, int64_t lam_stride, const int32_t* iters, const double* sqrt_lam,
+                              const double* basis, int n, int kl, int K, double* grad, int64_t N, hipStream_t s);
+hipError_t launch_pcnl_propose(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr,
+                               const double* xi, const double* grad, double* v, hipStream_t s);
+hipError_t launch_pcnl_accept(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr, const double* v,
+                              const double* gnew, const double* phinew, const int32_t* iters_new, double* xi,
+                              double* grad, double* phi, int32_t* n_acc, hipStream_t s);
 hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStream_t s);
 hipError_t launch_solve1d(int n, int64_t N, const SolveArgs& a, hipStream_t s);
 bool dst_supported(int n);

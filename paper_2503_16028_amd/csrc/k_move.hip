@@ -196,6 +196,101 @@ hipError_t launch_accept(int64_t N, int K, double tau, uint64_t seed, uint64_t c
     return hipGetLastError();
 }
 
+// pCN-Langevin proposal in whitened coordinates (Sec. 2.4 names the move; App. B gives the
+// Langevin equation and its Crank-Nicolson step, here with the tempered potential's drift kept
+// explicit):  v = gamma xi - (1 - gamma) tau g(xi) + beta z,  g = grad_xi Phi,  gamma^2 + beta^2 = 1.
+// Normal i of a particle is element i % 2 of block i / 2, as for the prior draw.
+__global__ __launch_bounds__(256) void pcnl_propose_kernel(int64_t N, int K, double beta, double tau, uint64_t seed,
+                                                           uint64_t ctr, const double* __restrict__ xi,
+                                                           const double* __restrict__ grad,
+                                                           double* __restrict__ v) {
+    const int nb = (K + 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= N * nb) return;
+    const int64_t n = t / nb;
+    const int blk = (int)(t % nb);
+    const double gamma = sqrt(1.0 - beta * beta), drift = (1.0 - gamma) * tau;
+    double z[2];
+    box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = 2 * blk + h;
+        if (k < K) v[n * K + k] = gamma * xi[n * K + k] - drift * grad[n * K + k] + beta * z[h];
+    }
+}
+
+hipError_t launch_pcnl_propose(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr,
+                               const double* xi, const double* grad, double* v, hipStream_t s) {
+    const int64_t work = N * ((K + 1) / 2);
+    if (work <= 0) return hipSuccess;
+    pcnl_propose_kernel<<<dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s>>>(N, K, beta, tau, seed, ctr, xi,
+                                                                                  grad, v);
+    return hipGetLastError();
+}
+
+// pCN-Langevin decision: the Metropolis-Hastings ratio of Sec. 2.3 with the Langevin kernel,
+// i.e. the plain ratio of densities in whitened coordinates,
+//   log r = [-tau Phi(v) - |v|^2/2 - |xi - m(v)|^2 / (2 beta^2)]
+//         - [-tau Phi(xi) - |xi|^2/2 - |v - m(xi)|^2 / (2 beta^2)],  m(a) = gamma a - (1 - gamma) tau g(a),
+// summed over the K modes in a fixed order; accept iff log U_acc < min(0, log r).  A proposal
+// whose forward or adjoint solve failed (iters < 0) or whose potential is not finite is rejected.
+__global__ __launch_bounds__(256) void pcnl_accept_kernel(int K, double beta, double tau, uint64_t seed, uint64_t ctr,
+                                                          const double* __restrict__ v,
+                                                          const double* __restrict__ gnew,
+                                                          const double* __restrict__ phinew,
+                                                          const int32_t* __restrict__ iters_new,
+                                                          double* __restrict__ xi, double* __restrict__ grad,
+                                                          double* __restrict__ phi, int32_t* __restrict__ n_acc) {
+    __shared__ double red[4];
+    __shared__ int acc;
+    const int64_t n = blockIdx.x;
+    const double gamma = sqrt(1.0 - beta * beta), drift = (1.0 - gamma) * tau;
+    const double inv2b2 = 0.5 / (beta * beta);
+    const double* xp = xi + n * K;
+    const double* gp = grad + n * K;
+    const double* vp = v + n * K;
+    const double* hp = gnew + n * K;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < K; k += 256) {
+        const double a = xp[k], b = vp[k];
+        const double back = a - (gamma * b - drift * hp[k]);   // xi - m(v)
+        const double fwd = b - (gamma * a - drift * gp[k]);    // v - m(xi)
+        s += 0.5 * (a * a - b * b) + (fwd * fwd - back * back) * inv2b2;
+    }
+    const double lr = block_sum<4>(s, red);
+    if (threadIdx.x == 0) {
+        const uint4 wd = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const double ua = res53(wd.z, wd.w);
+        const double pn = phinew[n];
+        bool ok = false;
+        if (isfinite(pn) && iters_new[n] >= 0) {
+            const double la = fmin(0.0, tau * (phi[n] - pn) + lr);
+            ok = log(ua) < la;
+        }
+        acc = ok;
+        if (ok) {
+            phi[n] = pn;
+            n_acc[n] += 1;
+        }
+    }
+    __syncthreads();
+    if (acc) {
+        for (int k = threadIdx.x; k < K; k += 256) {
+            xi[n * K + k] = vp[k];
+            grad[n * K + k] = hp[k];
+        }
+    }
+}
+
+hipError_t launch_pcnl_accept(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr, const double* v,
+                              const double* gnew, const double* phinew, const int32_t* iters_new, double* xi,
+                              double* grad, double* phi, int32_t* n_acc, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    pcnl_accept_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, beta, tau, seed, ctr, v, gnew, phinew, iters_new,
+                                                               xi, grad, phi, n_acc);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void gather_kernel(int64_t N, int K, const int32_t* __restrict__ idx,
                                                      const double* __restrict__ xi_in,
                                                      const double* __restrict__ phi_in, double* __restrict__ xi_out,

@@ -164,7 +164,7 @@ hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const vo
     return hipGetLastError();
 }
 
-template <typename T, int NN, int R, bool DST>
+template <typename T, int NN, int R, bool DST, bool ADJ>
 __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf16* __restrict__ Stab,
                                                          const float* __restrict__ lamtab) {
     constexpr int NT = NN * NN / R;
@@ -177,6 +177,8 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
     static_assert(!DST || (NN >= 32 && (DS::NB * DS::NB) % NW == 0 && NW % DS::NB == 0), "transform tiling");
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ double red1[NW], red2[NW];
+    __shared__ double src_w[MAX_OBS];   // adjoint point sources: weight and unknown index (-1: none)
+    __shared__ int src_at[MAX_OBS];
     T* ly = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
     const int64_t row = blockIdx.x;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
-    double* sd = a.sd + row * a.x_stride;
+    double* sd = a.sd + row * a.sd_stride;
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     // own node of row r: tb[NN + 1 + r * NN]; east +1, west -1, north +NN, south -NN
     T* tb = ly + PAD + b * R * NN + c - NN - 1;
@@ -236,177 +238,212 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
             return T(0);
         }
     };
+    // observations of the forward solution: G, Phi, and the adjoint's sources (G - y) / sigma^2
+    auto observe = [&](bool good) {
+        __syncthreads();
+        double val = 0.0;
+        if (tid < a.n_obs) {
+            const int node = a.obs[tid];
+            const int jj = node / NP1, ii = node % NP1;
+            const bool in = ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1;
+            if (in) val = x64[(jj - 1) * NN + ii - 1];
+            if (!good) val = NAN;
+            if (a.G) a.G[row * a.n_obs + tid] = val;
+            src_w[tid] = 2.0 * a.inv2s2 * (val - a.y[tid]);
+            src_at[tid] = in ? (jj - 1) * NN + ii - 1 : -1;
+        }
+        if (tid < 64) {
+            const double dlt = (tid < a.n_obs) ? val - a.y[tid] : 0.0;
+            const double s = wave_sum(dlt * dlt);
+            if (tid == 0 && a.phi) a.phi[row] = good ? s * a.inv2s2 : INFINITY;
+        }
+        __syncthreads();
+    };
 
-    // ---- refinement sweeps
-    const double fnorm = fabs(a.f) * (double)(NN - 1);
-    int total = 0, sweeps = 0;
-    bool ok = false;
+    // ---- pass 0: forward problem A w = f into x64 (skipped when x64 already holds w);
+    //      pass 1 (ADJ): adjoint problem A lam = P^T (P w - y) / sigma^2 into a.lam
+    const int first = (ADJ && a.fwd_given) ? 1 : 0, last = ADJ ? 1 : 0;
+    int total = 0, sweeps = 0, solves = 0;
+    bool ok = true;
     T x[R], rv[R], p[R], q[R];
-    for (int sweep = 0;; ++sweep) {
-        sweeps = sweep;
-        double acc = 0.0;
-        if (sweep == 0) {
+#pragma unroll 1
+    for (int pass_ = first; pass_ <= last && ok; ++pass_) {
+        const int pass = ADJ ? pass_ : 0;
+        if (pass == 1 && first == 1) observe(true);
+        double* xo = pass ? a.lam + row * a.lam_stride : x64;
+        auto rhs = [&](int flat) __attribute__((always_inline)) -> double {
+            if (pass == 0) return a.f;
+            double s = 0.0;
+            for (int k = 0; k < a.n_obs; ++k) s += (src_at[k] == flat) ? src_w[k] : 0.0;
+            return s;
+        };
+        ok = false;
+        double fnorm = 0.0;
+        // ---- refinement sweeps
+        for (int sweep = 0;; ++sweep) {
+            ++sweeps;
+            double acc = 0.0;
+            if (sweep == 0) {
+#pragma unroll 1
+                for (int r = 0; r < R; ++r) {
+                    const int g = b * R + r;
+                    T out = T(0);
+                    if (c < NN - 1 && g < NN - 1) {
+                        const double f = rhs(g * NN + c);
+                        acc += f * f;
+                        out = (T)(sd[g * NN + c] * f);
+                    }
+                    tb[NN + 1 + r * NN] = out;
+                }
+            } else {
+                // r = f - A x in FP64; column i of e and x carried along the strip
+                const int g0 = b * R;
+                double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
+                double xS = (g0 > 0 && c < NN - 1) ? xo[(g0 - 1) * NN + c] : 0.0;
+                double xC = (g0 < NN - 1 && c < NN - 1) ? xo[g0 * NN + c] : 0.0;
+#pragma unroll 1
+                for (int r = 0; r < R; ++r) {
+                    const int g = g0 + r, j = g + 1;
+                    const double eN = (j + 1 <= NN) ? e[(j + 1) * NP1 + i] : 0.0;
+                    const double xN = (g + 1 < NN - 1 && c < NN - 1) ? xo[(g + 1) * NN + c] : 0.0;
+                    T out = T(0);
+                    if (c < NN - 1 && g < NN - 1) {
+                        const double xE = (c + 1 < NN - 1) ? xo[g * NN + c + 1] : 0.0;
+                        const double xW = (c > 0) ? xo[g * NN + c - 1] : 0.0;
+                        const double res = rhs(g * NN + c) -
+                                           eC * inv_h2 *
+                                               (e[j * NP1 + i + 1] * (xC - xE) + e[j * NP1 + i - 1] * (xC - xW) +
+                                                eN * (xC - xN) + eS * (xC - xS));
+                        acc += res * res;
+                        out = (T)(sd[g * NN + c] * res);
+                    }
+                    tb[NN + 1 + r * NN] = out;
+                    eS = eC;
+                    eC = eN;
+                    xS = xC;
+                    xC = xN;
+                }
+            }
+            const double rr64 = block_sum<NW>(acc, red2);
+            if (sweep == 0) fnorm = sqrt(rr64);
+            if (sqrt(rr64) <= a.tol64 * fnorm) {   // at sweep 0 only for a zero right-hand side
+                ok = true;
+                if (sweep == 0) {
+#pragma unroll 1
+                    for (int r = 0; r < R; ++r) xo[(b * R + r) * NN + c] = 0.0;
+                }
+                break;
+            }
+            if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
+
+            double tacc = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                rv[r] = tb[NN + 1 + r * NN];
+                x[r] = T(0);
+                tacc += (double)rv[r] * (double)rv[r];
+            }
+            double rr, rz;
+            if constexpr (DST) {
+                __syncthreads();                  // the transform buffers alias the staging slots
+                precondition(rv);
+                double zacc = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    p[r] = zval(r);
+                    zacc += (double)rv[r] * (double)p[r];
+                }
+                rr = block_sum<NW>(tacc, red1);
+                rz = block_sum<NW>(zacc, red2);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[r] = rv[r];
+                rr = block_sum<NW>(tacc, red1);
+                rz = rr;
+            }
+            const double target = a.tol_inner * a.tol_inner * rr;
+            bool broke = false;
+            while (rr > target) {
+                if (total >= a.max_iter) break;
+#pragma unroll
+                for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = t[r] * p[r];
+                if constexpr (DST) {   // the transform buffers alias the padding: zero it again
+                    for (int k = tid; k < PAD; k += NT) {
+                        ly[k] = T(0);
+                        ly[PAD + NN * NN + k] = T(0);
+                    }
+                }
+                __syncthreads();
+                T pq_acc = T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T yE = tb[NN + 2 + r * NN];
+                    const T yW = tb[NN + r * NN];
+                    const T yN = (r + 1 < R) ? t[r + 1] * p[r + 1] : tb[NN + 1 + R * NN];
+                    const T yS = (r > 0) ? t[r - 1] * p[r - 1] : tb[1];
+                    q[r] = p[r] - t[r] * ((yE + yW) + (yN + yS));
+                    pq_acc += p[r] * q[r];
+                }
+                const double pq = block_sum<NW>((double)pq_acc, red1);
+                if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
+                const T alpha = (T)(rz / pq);
+                T r_acc = T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    x[r] += alpha * p[r];
+                    rv[r] -= alpha * q[r];
+                    r_acc += rv[r] * rv[r];
+                }
+                rr = block_sum<NW>((double)r_acc, red2);
+                ++total;
+                if (!(rr > target)) break;
+                if constexpr (DST) {
+                    precondition(rv);
+                    T z[R];
+                    T rz_acc = T(0);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        z[r] = zval(r);
+                        rz_acc += rv[r] * z[r];
+                    }
+                    const double rzn = block_sum<NW>((double)rz_acc, red1);
+                    const T beta = (T)(rzn / rz);
+                    rz = rzn;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) p[r] = z[r] + beta * p[r];
+                } else {
+                    const T beta = (T)(rr / rz);
+                    rz = rr;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) p[r] = rv[r] + beta * p[r];
+                }
+            }
+            // xo += D^{-1/2} y, staged through the thread's own LDS slots
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = x[r];
 #pragma unroll 1
             for (int r = 0; r < R; ++r) {
                 const int g = b * R + r;
-                T out = T(0);
-                if (c < NN - 1 && g < NN - 1) {
-                    acc += a.f * a.f;
-                    out = (T)(sd[g * NN + c] * a.f);
-                }
-                tb[NN + 1 + r * NN] = out;
-            }
-        } else {
-            // r = f - A x in FP64; column i of e and x carried along the strip
-            const int g0 = b * R;
-            double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
-            double xS = (g0 > 0 && c < NN - 1) ? x64[(g0 - 1) * NN + c] : 0.0;
-            double xC = (g0 < NN - 1 && c < NN - 1) ? x64[g0 * NN + c] : 0.0;
-#pragma unroll 1
-            for (int r = 0; r < R; ++r) {
-                const int g = g0 + r, j = g + 1;
-                const double eN = (j + 1 <= NN) ? e[(j + 1) * NP1 + i] : 0.0;
-                const double xN = (g + 1 < NN - 1 && c < NN - 1) ? x64[(g + 1) * NN + c] : 0.0;
-                T out = T(0);
-                if (c < NN - 1 && g < NN - 1) {
-                    const double xE = (c + 1 < NN - 1) ? x64[g * NN + c + 1] : 0.0;
-                    const double xW = (c > 0) ? x64[g * NN + c - 1] : 0.0;
-                    const double res = a.f - eC * inv_h2 *
-                                                 (e[j * NP1 + i + 1] * (xC - xE) + e[j * NP1 + i - 1] * (xC - xW) +
-                                                  eN * (xC - xN) + eS * (xC - xS));
-                    acc += res * res;
-                    out = (T)(sd[g * NN + c] * res);
-                }
-                tb[NN + 1 + r * NN] = out;
-                eS = eC;
-                eC = eN;
-                xS = xC;
-                xC = xN;
-            }
-        }
-        const double rr64 = block_sum<NW>(acc, red2);
-        if (sqrt(rr64) <= a.tol64 * fnorm) { ok = true; break; }
-        if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
-
-        double tacc = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            rv[r] = tb[NN + 1 + r * NN];
-            x[r] = T(0);
-            tacc += (double)rv[r] * (double)rv[r];
-        }
-        double rr, rz;
-        if constexpr (DST) {
-            __syncthreads();                  // the transform buffers alias the staging slots
-            precondition(rv);
-            double zacc = 0.0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                p[r] = zval(r);
-                zacc += (double)rv[r] * (double)p[r];
-            }
-            rr = block_sum<NW>(tacc, red1);
-            rz = block_sum<NW>(zacc, red2);
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) p[r] = rv[r];
-            rr = block_sum<NW>(tacc, red1);
-            rz = rr;
-        }
-        const double target = a.tol_inner * a.tol_inner * rr;
-        bool broke = false;
-        while (rr > target) {
-            if (total >= a.max_iter) break;
-#pragma unroll
-            for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = t[r] * p[r];
-            if constexpr (DST) {   // the transform buffers alias the padding: zero it again
-                for (int k = tid; k < PAD; k += NT) {
-                    ly[k] = T(0);
-                    ly[PAD + NN * NN + k] = T(0);
-                }
+                const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
+                xo[g * NN + c] = (sweep == 0) ? corr : xo[g * NN + c] + corr;
             }
             __syncthreads();
-            T pq_acc = T(0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T yE = tb[NN + 2 + r * NN];
-                const T yW = tb[NN + r * NN];
-                const T yN = (r + 1 < R) ? t[r + 1] * p[r + 1] : tb[NN + 1 + R * NN];
-                const T yS = (r > 0) ? t[r - 1] * p[r - 1] : tb[1];
-                q[r] = p[r] - t[r] * ((yE + yW) + (yN + yS));
-                pq_acc += p[r] * q[r];
-            }
-            const double pq = block_sum<NW>((double)pq_acc, red1);
-            if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
-            const T alpha = (T)(rz / pq);
-            T r_acc = T(0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                x[r] += alpha * p[r];
-                rv[r] -= alpha * q[r];
-                r_acc += rv[r] * rv[r];
-            }
-            rr = block_sum<NW>((double)r_acc, red2);
-            ++total;
-            if (!(rr > target)) break;
-            if constexpr (DST) {
-                precondition(rv);
-                T z[R];
-                T rz_acc = T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    z[r] = zval(r);
-                    rz_acc += rv[r] * z[r];
-                }
-                const double rzn = block_sum<NW>((double)rz_acc, red1);
-                const T beta = (T)(rzn / rz);
-                rz = rzn;
-#pragma unroll
-                for (int r = 0; r < R; ++r) p[r] = z[r] + beta * p[r];
-            } else {
-                const T beta = (T)(rr / rz);
-                rz = rr;
-#pragma unroll
-                for (int r = 0; r < R; ++r) p[r] = rv[r] + beta * p[r];
-            }
+            if (broke) break;
         }
-        // x64 += D^{-1/2} y, staged through the thread's own LDS slots
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = x[r];
-#pragma unroll 1
-        for (int r = 0; r < R; ++r) {
-            const int g = b * R + r;
-            const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
-            x64[g * NN + c] = (sweep == 0) ? corr : x64[g * NN + c] + corr;
-        }
-        __syncthreads();
-        if (broke) break;
+        ++solves;
+        if (pass == 0) observe(ok);
     }
 
-    // ---- observation, potential, bookkeeping
-    __syncthreads();
-    double val = 0.0;
-    if (tid < a.n_obs) {
-        const int node = a.obs[tid];
-        const int jj = node / NP1, ii = node % NP1;
-        if (ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1) val = x64[(jj - 1) * NN + ii - 1];
-        if (!ok) val = NAN;
-        if (a.G) a.G[row * a.n_obs + tid] = val;
-    }
-    if (tid < 64) {
-        const double dlt = (tid < a.n_obs) ? val - a.y[tid] : 0.0;
-        const double s = wave_sum(dlt * dlt);
-        if (tid == 0) {
-            if (a.phi) a.phi[row] = ok ? s * a.inv2s2 : INFINITY;
-            if (a.iters) a.iters[row] = ok ? total : -1;
-            if (!ok) atomicOr(a.flags, SMC_FLAG_NOCONV);
-            if (a.stats) {
-                atomicAdd(&a.stats[0], (unsigned long long)total);
-                atomicAdd(&a.stats[1], (unsigned long long)(sweeps + 1));
-                atomicAdd(&a.stats[2], 1ull);
-                atomicAdd(&a.stats[3], (unsigned long long)napp);
-            }
+    // ---- bookkeeping
+    if (tid == 0) {
+        if (a.iters) a.iters[row] = ok ? total : -1;
+        if (!ok) atomicOr(a.flags, SMC_FLAG_NOCONV);
+        if (a.stats) {
+            atomicAdd(&a.stats[0], (unsigned long long)total);
+            atomicAdd(&a.stats[1], (unsigned long long)sweeps);
+            atomicAdd(&a.stats[2], (unsigned long long)solves);
+            atomicAdd(&a.stats[3], (unsigned long long)napp);
         }
     }
 }
@@ -414,17 +451,19 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
 // Same method (Jacobi-scaled CG, product form) with every vector in global memory, for grids
 // whose vectors do not fit in one workgroup's registers and LDS; 1024 threads stride over
 // the nodes of one particle.
-template <typename T>
+template <typename T, bool ADJ>
 __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
     constexpr int NW = 16;
     __shared__ double red1[NW], red2[NW];
+    __shared__ double src_w[MAX_OBS];
+    __shared__ int src_at[MAX_OBS];
     const int tid = threadIdx.x;
     const int NP1 = NN + 1;
     const int nodes = NN * NN;
     const int64_t row = blockIdx.x;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
-    double* sd = a.sd + row * a.x_stride;
+    double* sd = a.sd + row * a.sd_stride;
     T* vb = reinterpret_cast<T*>(reinterpret_cast<double*>(a.vec) + row * a.vec_stride);
     T* tv = vb;
     T* xv = vb + nodes;
@@ -449,107 +488,137 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
     }
     __syncthreads();
 
-    const double fnorm = fabs(a.f) * (double)(NN - 1);
-    int total = 0, sweeps = 0;
-    bool ok = false;
-    for (int sweep = 0;; ++sweep) {
-        sweeps = sweep;
-        double acc = 0.0;
-        for (int k = tid; k < nodes; k += 1024) {
-            const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
-            T rk = T(0);
-            if (interior(g, c)) {
-                double res = a.f;
-                if (sweep > 0) {
-                    const double xP = x64[k];
-                    const double xE = (c + 1 < NN - 1) ? x64[k + 1] : 0.0;
-                    const double xW = (c > 0) ? x64[k - 1] : 0.0;
-                    const double xN = (g + 1 < NN - 1) ? x64[k + NN] : 0.0;
-                    const double xS = (g > 0) ? x64[k - NN] : 0.0;
-                    res -= e[j * NP1 + i] * inv_h2 *
-                           (e[j * NP1 + i + 1] * (xP - xE) + e[j * NP1 + i - 1] * (xP - xW) +
-                            e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
-                }
-                acc += res * res;
-                rk = (T)(sd[k] * res);
-            }
-            rv[k] = rk;
-            pv[k] = rk;
-            xv[k] = T(0);
+    // observations of the forward solution: G, Phi, and the adjoint's sources (G - y) / sigma^2
+    auto observe = [&](bool good) {
+        __syncthreads();
+        double val = 0.0;
+        if (tid < a.n_obs) {
+            const int node = a.obs[tid];
+            const int jj = node / NP1, ii = node % NP1;
+            const bool in = ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1;
+            if (in) val = x64[(jj - 1) * NN + ii - 1];
+            if (!good) val = NAN;
+            if (a.G) a.G[row * a.n_obs + tid] = val;
+            src_w[tid] = 2.0 * a.inv2s2 * (val - a.y[tid]);
+            src_at[tid] = in ? (jj - 1) * NN + ii - 1 : -1;
         }
-        const double rr64 = block_sum<NW>(acc, red2);
-        if (sqrt(rr64) <= a.tol64 * fnorm) { ok = true; break; }
-        if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
-
-        double tacc = 0.0;
-        for (int k = tid; k < nodes; k += 1024) tacc += (double)rv[k] * (double)rv[k];
-        double rr = block_sum<NW>(tacc, red1);
-        const double target = a.tol_inner * a.tol_inner * rr;
-        bool broke = false;
-        while (rr > target) {
-            if (total >= a.max_iter) break;
-            for (int k = tid; k < nodes; k += 1024) yv[k] = tv[k] * pv[k];
-            __syncthreads();
-            T pq_acc = T(0);
-            for (int k = tid; k < nodes; k += 1024) {
-                const int g = k / NN, c = k % NN;
-                T qk = T(0);
-                const T pk = pv[k];
-                if (interior(g, c)) {
-                    const T yE = yv[k + 1];
-                    const T yW = (c > 0) ? yv[k - 1] : T(0);
-                    const T yN = yv[k + NN];
-                    const T yS = (g > 0) ? yv[k - NN] : T(0);
-                    qk = pk - tv[k] * ((yE + yW) + (yN + yS));
-                }
-                qv[k] = qk;
-                pq_acc += pk * qk;
-            }
-            const double pq = block_sum<NW>((double)pq_acc, red1);
-            if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
-            const T alpha = (T)(rr / pq);
-            T r_acc = T(0);
-            for (int k = tid; k < nodes; k += 1024) {
-                xv[k] += alpha * pv[k];
-                const T rk = rv[k] - alpha * qv[k];
-                rv[k] = rk;
-                r_acc += rk * rk;
-            }
-            const double rrn = block_sum<NW>((double)r_acc, red2);
-            const T beta = (T)(rrn / rr);
-            rr = rrn;
-            for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
-            ++total;
-        }
-        for (int k = tid; k < nodes; k += 1024) {
-            const double corr = sd[k] * (double)xv[k];
-            x64[k] = (sweep == 0) ? corr : x64[k] + corr;
+        if (tid < 64) {
+            const double dlt = (tid < a.n_obs) ? val - a.y[tid] : 0.0;
+            const double s = wave_sum(dlt * dlt);
+            if (tid == 0 && a.phi) a.phi[row] = good ? s * a.inv2s2 : INFINITY;
         }
         __syncthreads();
-        if (broke) break;
+    };
+
+    // pass 0: forward problem into x64 (skipped when given); pass 1 (ADJ): adjoint problem into a.lam
+    const int first = (ADJ && a.fwd_given) ? 1 : 0, last = ADJ ? 1 : 0;
+    int total = 0, sweeps = 0, solves = 0;
+    bool ok = true;
+    for (int pass_ = first; pass_ <= last && ok; ++pass_) {
+        const int pass = ADJ ? pass_ : 0;
+        if (pass == 1 && first == 1) observe(true);
+        double* xo = pass ? a.lam + row * a.lam_stride : x64;
+        auto rhs = [&](int flat) -> double {
+            if (pass == 0) return a.f;
+            double s = 0.0;
+            for (int k = 0; k < a.n_obs; ++k) s += (src_at[k] == flat) ? src_w[k] : 0.0;
+            return s;
+        };
+        ok = false;
+        double fnorm = 0.0;
+        for (int sweep = 0;; ++sweep) {
+            ++sweeps;
+            double acc = 0.0;
+            for (int k = tid; k < nodes; k += 1024) {
+                const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
+                T rk = T(0);
+                if (interior(g, c)) {
+                    double res = rhs(k);
+                    if (sweep > 0) {
+                        const double xP = xo[k];
+                        const double xE = (c + 1 < NN - 1) ? xo[k + 1] : 0.0;
+                        const double xW = (c > 0) ? xo[k - 1] : 0.0;
+                        const double xN = (g + 1 < NN - 1) ? xo[k + NN] : 0.0;
+                        const double xS = (g > 0) ? xo[k - NN] : 0.0;
+                        res -= e[j * NP1 + i] * inv_h2 *
+                               (e[j * NP1 + i + 1] * (xP - xE) + e[j * NP1 + i - 1] * (xP - xW) +
+                                e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
+                    }
+                    acc += res * res;
+                    rk = (T)(sd[k] * res);
+                }
+                rv[k] = rk;
+                pv[k] = rk;
+                xv[k] = T(0);
+            }
+            const double rr64 = block_sum<NW>(acc, red2);
+            if (sweep == 0) fnorm = sqrt(rr64);
+            if (sqrt(rr64) <= a.tol64 * fnorm) {   // at sweep 0 only for a zero right-hand side
+                ok = true;
+                if (sweep == 0)
+                    for (int k = tid; k < nodes; k += 1024) xo[k] = 0.0;
+                break;
+            }
+            if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
+
+            double tacc = 0.0;
+            for (int k = tid; k < nodes; k += 1024) tacc += (double)rv[k] * (double)rv[k];
+            double rr = block_sum<NW>(tacc, red1);
+            const double target = a.tol_inner * a.tol_inner * rr;
+            bool broke = false;
+            while (rr > target) {
+                if (total >= a.max_iter) break;
+                for (int k = tid; k < nodes; k += 1024) yv[k] = tv[k] * pv[k];
+                __syncthreads();
+                T pq_acc = T(0);
+                for (int k = tid; k < nodes; k += 1024) {
+                    const int g = k / NN, c = k % NN;
+                    T qk = T(0);
+                    const T pk = pv[k];
+                    if (interior(g, c)) {
+                        const T yE = yv[k + 1];
+                        const T yW = (c > 0) ? yv[k - 1] : T(0);
+                        const T yN = yv[k + NN];
+                        const T yS = (g > 0) ? yv[k - NN] : T(0);
+                        qk = pk - tv[k] * ((yE + yW) + (yN + yS));
+                    }
+                    qv[k] = qk;
+                    pq_acc += pk * qk;
+                }
+                const double pq = block_sum<NW>((double)pq_acc, red1);
+                if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
+                const T alpha = (T)(rr / pq);
+                T r_acc = T(0);
+                for (int k = tid; k < nodes; k += 1024) {
+                    xv[k] += alpha * pv[k];
+                    const T rk = rv[k] - alpha * qv[k];
+                    rv[k] = rk;
+                    r_acc += rk * rk;
+                }
+                const double rrn = block_sum<NW>((double)r_acc, red2);
+                const T beta = (T)(rrn / rr);
+                rr = rrn;
+                for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
+                ++total;
+            }
+            for (int k = tid; k < nodes; k += 1024) {
+                const double corr = sd[k] * (double)xv[k];
+                xo[k] = (sweep == 0) ? corr : xo[k] + corr;
+            }
+            __syncthreads();
+            if (broke) break;
+        }
+        ++solves;
+        if (pass == 0) observe(ok);
     }
 
-    __syncthreads();
-    double val = 0.0;
-    if (tid < a.n_obs) {
-        const int node = a.obs[tid];
-        const int jj = node / NP1, ii = node % NP1;
-        if (ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1) val = x64[(jj - 1) * NN + ii - 1];
-        if (!ok) val = NAN;
-        if (a.G) a.G[row * a.n_obs + tid] = val;
-    }
-    if (tid < 64) {
-        const double dlt = (tid < a.n_obs) ? val - a.y[tid] : 0.0;
-        const double s = wave_sum(dlt * dlt);
-        if (tid == 0) {
-            if (a.phi) a.phi[row] = ok ? s * a.inv2s2 : INFINITY;
-            if (a.iters) a.iters[row] = ok ? total : -1;
-            if (!ok) atomicOr(a.flags, SMC_FLAG_NOCONV);
-            if (a.stats) {
-                atomicAdd(&a.stats[0], (unsigned long long)total);
-                atomicAdd(&a.stats[1], (unsigned long long)(sweeps + 1));
-                atomicAdd(&a.stats[2], 1ull);
-            }
+    if (tid == 0) {
+        if (a.iters) a.iters[row] = ok ? total : -1;
+        if (!ok) atomicOr(a.flags, SMC_FLAG_NOCONV);
+        if (a.stats) {
+            atomicAdd(&a.stats[0], (unsigned long long)total);
+            atomicAdd(&a.stats[1], (unsigned long long)sweeps);
+            atomicAdd(&a.stats[2], (unsigned long long)solves);
         }
     }
 }
@@ -589,8 +658,20 @@ __global__ __launch_bounds__(256) void solve1d_kernel(SolveArgs a, int n, int64_
 
 template <typename T, int NN, int R, bool DST>
 static hipError_t run_onchip(int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
-    cg_onchip<T, NN, R, DST><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, reinterpret_cast<const __bf16*>(S),
-                                                                          lam);
+    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+    if (a.lam)
+        cg_onchip<T, NN, R, DST, true><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, Sb, lam);
+    else
+        cg_onchip<T, NN, R, DST, false><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, Sb, lam);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t run_global(int64_t N, const SolveArgs& a, int n, hipStream_t s) {
+    if (a.lam)
+        cg_global<T, true><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, n);
+    else
+        cg_global<T, false><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, n);
     return hipGetLastError();
 }
 
@@ -614,9 +695,7 @@ hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStr
             case 32: return run_onchip<float, 32, 4, false>(N, a, nullptr, nullptr, s);
             case 64: return run_onchip<float, 64, 8, false>(N, a, nullptr, nullptr, s);
             case 128: return run_onchip<float, 128, 16, false>(N, a, nullptr, nullptr, s);
-            default:
-                cg_global<float><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, n);
-                return hipGetLastError();
+            default: return run_global<float>(N, a, n, s);
         }
     }
     SolveArgs b = a;
@@ -625,9 +704,7 @@ hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStr
         case 16: return run_onchip<double, 16, 4, false>(N, b, nullptr, nullptr, s);
         case 32: return run_onchip<double, 32, 4, false>(N, b, nullptr, nullptr, s);
         case 64: return run_onchip<double, 64, 8, false>(N, b, nullptr, nullptr, s);
-        default:
-            cg_global<double><<<dim3((unsigned)N), dim3(1024), 0, s>>>(b, n);
-            return hipGetLastError();
+        default: return run_global<double>(N, b, n, s);
     }
 }
 

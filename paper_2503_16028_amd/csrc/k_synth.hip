@@ -94,6 +94,103 @@ __global__ __launch_bounds__(256) void synth1d_kernel(const double* __restrict__
     }
 }
 
+// Gradient of Phi with respect to the whitened coefficients from the forward solution w and the
+// adjoint solution lam (the extra solve of gradient-informed moves, Sec. 2.4).  With
+// A(u) w = f and lam^T A w = sum over faces (P,Q) of a_PQ (lam_P - lam_Q)(w_P - w_Q) / h^2,
+// d a_PQ / d u_P = a_PQ / 2 gives at every node P (boundary nodes included, w = lam = 0 there)
+//   dU[P] = dPhi/du_P = -(1/2) sum_{Q nbr P} a_PQ (lam_P - lam_Q)(w_P - w_Q) / h^2,  a_PQ = e_P e_Q,
+// and the transpose of the separable synthesis gives
+//   g_kl = sqrt(lambda_kl) sum_j sum_i B[i][k] dU[j][i] B[j][l].
+// dU is formed 32 grid rows at a time in LDS and contracted on the FP64 matrix cores:
+//   T[j][k] = sum_i dU[j][i] B[i][k] for the block's rows j, then H[k][l] += sum_j T[j][k] B[j][l].
+// A particle whose solves did not converge (iters < 0) gets a NaN gradient.
+__global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restrict__ e, int64_t e_stride,
+                                                          const double* __restrict__ w, int64_t w_stride,
+                                                          const double* __restrict__ lam, int64_t lam_stride,
+                                                          const int32_t* __restrict__ iters,
+                                                          const double* __restrict__ sqrt_lam,
+                                                          const double* __restrict__ basis, int n, int kl, int K,
+                                                          double* __restrict__ grad) {
+    extern __shared__ double smem[];
+    const int np1 = n + 1;
+    const int ipad = (np1 + 3) & ~3;
+    const int LDD = ipad + 1;
+    constexpr int LDT = KLP + 1;
+    double* D = smem;                  // [32][LDD] dU of the block's rows
+    double* Tb = D + 32 * LDD;         // [32][LDT]
+    const int64_t p = blockIdx.x;
+    const double* ep = e + p * e_stride;
+    const double* wp = w + p * w_stride;
+    const double* lp = lam + p * lam_stride;
+    const double scale = -0.5 * (double)n * (double)n;
+    // interior values are stored at (j - 1) n + (i - 1); boundary nodes are zero
+    auto at = [&](const double* v, int j, int i) -> double {
+        return (i >= 1 && i < n && j >= 1 && j < n) ? v[(j - 1) * n + (i - 1)] : 0.0;
+    };
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tj0 = (wave >> 1) * 16, tk0 = (wave & 1) * 16;   // this wave's T tile (block rows, k)
+    const int hk0 = (wave & 1) * 16, hl0 = (wave >> 1) * 16;   // this wave's H tile (k, l)
+    d4 hacc = {0.0, 0.0, 0.0, 0.0};
+    for (int jb = 0; jb < np1; jb += 32) {
+        for (int t = threadIdx.x; t < 32 * ipad; t += 256) {
+            const int r = t / ipad, i = t % ipad, j = jb + r;
+            double v = 0.0;
+            if (j <= n && i <= n) {
+                const double wP = at(wp, j, i), lP = at(lp, j, i);
+                double acc = 0.0;
+                if (i > 0) acc += ep[j * np1 + i - 1] * (lP - at(lp, j, i - 1)) * (wP - at(wp, j, i - 1));
+                if (i < n) acc += ep[j * np1 + i + 1] * (lP - at(lp, j, i + 1)) * (wP - at(wp, j, i + 1));
+                if (j > 0) acc += ep[(j - 1) * np1 + i] * (lP - at(lp, j - 1, i)) * (wP - at(wp, j - 1, i));
+                if (j < n) acc += ep[(j + 1) * np1 + i] * (lP - at(lp, j + 1, i)) * (wP - at(wp, j + 1, i));
+                v = scale * ep[j * np1 + i] * acc;
+            }
+            D[r * LDD + i] = v;
+        }
+        __syncthreads();
+        {   // T[r][k] = sum_i D[r][i] B[i][k]
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int i0 = 0; i0 < ipad; i0 += 4) {
+                const int ii = i0 + lk;
+                const double av = D[(tj0 + lr) * LDD + ii];
+                const double bv = (ii <= n) ? basis[ii * KLP + tk0 + lr] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Tb[(tj0 + lk + 4 * v) * LDT + tk0 + lr] = acc[v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r0 = 0; r0 < 32; r0 += 4) {   // H[k][l] += sum_r T[r][k] B[jb + r][l]
+            const int jj = jb + r0 + lk;
+            const double av = Tb[(r0 + lk) * LDT + hk0 + lr];
+            const double bv = (jj <= n) ? basis[jj * KLP + hl0 + lr] : 0.0;
+            hacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, hacc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const bool bad = iters && iters[p] < 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int k = hk0 + lk + 4 * v, l = hl0 + lr;
+        if (k < kl && l < kl) grad[p * K + k * kl + l] = bad ? NAN : sqrt_lam[k * kl + l] * hacc[v];
+    }
+}
+
+hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w, int64_t w_stride,
+                              const double* lam, int64_t lam_stride, const int32_t* iters, const double* sqrt_lam,
+                              const double* basis, int n, int kl, int K, double* grad, int64_t N, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const int ipad = (n + 1 + 3) & ~3;
+    const size_t lds = sizeof(double) * (32 * (size_t)(ipad + 1) + 32 * (size_t)(KLP + 1));
+    hipError_t r = hipFuncSetAttribute((const void*)gradsynth2d_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (r != hipSuccess) return r;
+    gradsynth2d_kernel<<<dim3((unsigned)N), dim3(256), lds, s>>>(e, e_stride, w, w_stride, lam, lam_stride, iters,
+                                                                 sqrt_lam, basis, n, kl, K, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_lam, const double* basis, int n,
                           double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s) {
     if (N <= 0) return hipSuccess;

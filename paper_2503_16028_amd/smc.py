@@ -53,6 +53,9 @@ _SIGS = {
     "smc_potential": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "smc_gmpcn_move": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_dbl, c_dbl, c_i32, c_u64, c_u64, c_vp, c_i32,
                                c_vp, c_vp, c_vp, c_vp]),
+    "smc_forward_state": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "smc_value_and_grad": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "smc_pcnl_move": (c_i32, [c_vp, c_i64, c_dbl, c_dbl, c_i32, c_u64, c_u64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_temper": (c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_resample": (c_i32, [c_i64, c_vp, c_u64, c_vp, c_vp, c_vp]),
     "smc_gather": (c_i32, [c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -207,6 +210,32 @@ def smc_gmpcn_move(problem, N, gm, beta, tau, n_moves, seed, ctr, level, prec, x
                                 ctr, _ptr(level, torch.int32, N, "level", optional=True), prec,
                                 _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
                                 _ptr(n_acc, torch.int32, N, "n_acc"), _stream(stream)))
+
+
+def smc_forward_state(problem, N, xi, prec, G, w, iters=None, stream=None):
+    """w: [N][n][n] FP64 forward solutions of grid 0 (the checkpointed forward state)."""
+    n = problem.grids[0]
+    _check(lib().smc_forward_state(problem.handle, N, _ptr(xi, torch.float64, N * problem.K, "xi"), prec,
+                                   _ptr(G, torch.float64, N * problem.n_obs, "G", optional=True),
+                                   _ptr(w, torch.float64, N * n * n, "w"),
+                                   _ptr(iters, torch.int32, N, "iters", optional=True), _stream(stream)))
+
+
+def smc_value_and_grad(problem, N, xi, prec, w, phi, grad, iters=None, stream=None):
+    """Potential and dPhi/dxi by an adjoint solve; w = forward states from smc_forward_state or None."""
+    n = problem.grids[0]
+    _check(lib().smc_value_and_grad(problem.handle, N, _ptr(xi, torch.float64, N * problem.K, "xi"), prec,
+                                    _ptr(w, torch.float64, N * n * n, "w", optional=True),
+                                    _ptr(phi, torch.float64, N, "phi", optional=True),
+                                    _ptr(grad, torch.float64, N * problem.K, "grad"),
+                                    _ptr(iters, torch.int32, N, "iters", optional=True), _stream(stream)))
+
+
+def smc_pcnl_move(problem, N, beta, tau, n_moves, seed, ctr, prec, xi, phi, grad, n_acc, stream=None):
+    _check(lib().smc_pcnl_move(problem.handle, N, float(beta), float(tau), int(n_moves), seed, ctr, prec,
+                               _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
+                               _ptr(grad, torch.float64, N * problem.K, "grad"), _ptr(n_acc, torch.int32, N, "n_acc"),
+                               _stream(stream)))
 
 
 def smc_temper(N, phi, tau_in, ess_frac, h, tau_new, W, log_z_inc, flags=None, stream=None):

@@ -75,3 +75,14 @@ def test_observation_must_be_a_node(libsmc):
     h = ctypes.c_void_p()
     assert libsmc.smc_problem_create(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"not a node" in libsmc.smc_last_error()
+
+
+def test_checkpoint_policy():
+    """'auto' keeps the FP64 forward states (8 n^2 bytes per particle) only when they fit."""
+    from paper_2503_16028_amd.autodiff import choose_checkpoint
+    assert choose_checkpoint("auto", 2048, 128, 2048 * 128 * 128 * 8) == "state"
+    assert choose_checkpoint("auto", 2048, 128, 2048 * 128 * 128 * 8 - 1) == "recompute"
+    assert choose_checkpoint("state", 10 ** 9, 256, 0) == "state"
+    assert choose_checkpoint("recompute", 1, 16, 1 << 40) == "recompute"
+    with pytest.raises(ValueError):
+        choose_checkpoint("keep", 1, 16, 0)
