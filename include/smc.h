@@ -46,6 +46,8 @@ typedef enum {
 #define SMC_FLAG_STALL 2
 #define SMC_FLAG_NONFINITE 4
 #define SMC_FLAG_BADWEIGHTS 8
+#define SMC_FLAG_BADLEVEL 16   /* a level map named a grid the problem does not have */
+#define SMC_FLAG_BADPARAM 32   /* a device-side beta or tau was out of range (moves rejected) */
 
 typedef enum {
     SMC_FP64 = 0,        /* conjugate gradients in FP64 */
@@ -54,6 +56,7 @@ typedef enum {
 
 typedef void* smc_stream; /* hipStream_t */
 typedef struct smc_problem_s* smc_problem;
+typedef struct smc_graph_s* smc_graph;   /* an instantiated, replayable move stage */
 
 /* Problem definition (host memory; copied by smc_problem_create).
  * Forward map (Sec. 3.2, eq. (example2:PDE), gradient on the state):
@@ -125,7 +128,10 @@ int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, do
                    smc_stream stream);
 
 /* Forward map G = F(u(xi)) for N particles (one PDE solve each, Sec. 3.2).
- *   level  [N] grid index per particle, or NULL for grid 0
+ *   level  [N] device, grid index per particle, or NULL for grid 0.  With a level map all
+ *          particles run in one persistent launch (2D, grids of 64, 128 and 256 intervals);
+ *          a particle whose level is out of range gets G = NaN, iters = -1 and sets
+ *          SMC_FLAG_BADLEVEL
  *   prec   smc_precision (1D problems always solve directly in FP64)
  *   G      [N][n_obs] out; NaN rows for solves that did not converge
  *   iters  [N] out, conjugate-gradient iterations, -1 when not converged; may be NULL */
@@ -148,6 +154,40 @@ int smc_potential(smc_problem p, int64_t N, const double* G, double* phi, smc_st
 int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
                    int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level,
                    int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
+
+/* Parameters of a move stage for several independent samplers at once, all in device memory
+ * so that a captured stage can be replayed after they change.  Group g (the particles with
+ * level[n] == g, or every particle without a level map) has its own mixture, beta and tau:
+ *   logw [G][M], mean [G][M][kr], scale [G][M][kr] (pad unused components with logw = -inf),
+ *   beta [G], tau [G], ctr [1] (move m draws from counter *ctr + m), all device pointers. */
+typedef struct {
+    int32_t n_groups; /* the problem's n_levels with a level map, else 1 */
+    int32_t M, kr;
+    const double* logw;
+    const double* mean;
+    const double* scale;
+    const double* beta;
+    const double* tau;
+    const uint64_t* ctr;
+    uint64_t seed;
+} smc_stage;
+
+/* n_moves pCN-GM steps as smc_gmpcn_move, with each particle's beta, tau and mixture taken
+ * from its group in `st`, read on the device when the kernels run.  Particles of a group with
+ * beta outside (0, 1] or tau outside [0, 1] keep their state and set SMC_FLAG_BADPARAM. */
+int smc_gmpcn_stage(smc_problem p, int64_t N, const int32_t* level, const smc_stage* st, int32_t n_moves,
+                    int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
+
+/* Capture smc_gmpcn_stage with these exact arguments (pointers and sizes) on `stream` (a created
+ * stream, not the null stream) into an instantiated HIP graph; nothing runs until it is launched.
+ * Each smc_stage_graph_launch replays the whole stage on `stream`: every kernel of every move
+ * in one submission, with the device-side parameters as they are at that time.  The graph
+ * uses the problem's workspace: replays and other calls on the same problem must not overlap. */
+int smc_stage_graph_create(smc_problem p, int64_t N, const int32_t* level, const smc_stage* st,
+                           int32_t n_moves, int32_t prec, double* xi, double* phi, int32_t* n_acc,
+                           smc_stream stream, smc_graph* out);
+int smc_stage_graph_launch(smc_graph g, smc_stream stream);
+void smc_stage_graph_destroy(smc_graph g);
 
 /* Forward solve that keeps its FP64 solution (the forward state of the adjoint gradient), on
  * grid 0 of a 2D problem: as smc_forward_batch, and w[N][n][n] out with element [g][c] the

@@ -21,6 +21,12 @@ struct smc_problem_s {
     Problem P;
     int device = 0;
     EventPool pool;
+    bool capturing = false;       // launches are being captured into a graph: no profiling events
+};
+
+struct smc_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 static thread_local std::string g_err;
@@ -56,7 +62,7 @@ static void free_problem(Problem& P) {
     f(P.sqrt_lam); f(P.active); f(P.slot); f(P.y);
     f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_lam); f(P.ws_gnew); f(P.ws_sd);
     f(P.ws_vec);
-    f(P.ws_G); f(P.ws_iters); f(P.flags); f(P.stats);
+    f(P.ws_G); f(P.ws_iters); f(P.ws_list); f(P.ws_counters); f(P.flags); f(P.stats);
 }
 
 extern "C" const char* smc_last_error(void) { return g_err.c_str(); }
@@ -138,6 +144,8 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
 
     hipError_t e = hipSuccess;
     auto ck = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    ck(prepare_kernels());
+    ck(hipDeviceGetAttribute(&P.n_cu, hipDeviceAttributeMultiprocessorCount, ps->device));
     ck(upload(&P.sqrt_lam, sl.data(), K));
     ck(upload(&P.active, act.data(), act.size()));
     ck(upload(&P.slot, slot.data(), slot.size()));
@@ -207,6 +215,9 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     if (P.dim == 2 && P.n_big >= 128) ck(hipMalloc(&P.ws_vec, sizeof(double) * Nm * P.vec_stride));
     ck(hipMalloc((void**)&P.ws_G, sizeof(double) * Nm * P.n_obs));
     ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
+    ck(hipMalloc((void**)&P.ws_list, sizeof(int32_t) * Nm));
+    ck(hipMalloc((void**)&P.ws_counters, 2 * sizeof(unsigned long long)));
+    ck(hipMemset(P.ws_counters, 0, 2 * sizeof(unsigned long long)));
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
     ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
@@ -359,6 +370,7 @@ static SolveArgs solve_args(const Problem& P, int level) {
 
 // Outputs and options of one batch of forward (and adjoint) solves; every pointer may be NULL.
 struct Solve {
+    const int32_t* level = nullptr;   // [N] grid of each particle (work list already planned), or null
     double* G = nullptr;
     double* phi = nullptr;
     int32_t* iters = nullptr;
@@ -368,8 +380,52 @@ struct Solve {
 };
 
 // Synthesis then solve for N particles of one grid.
+static LevelTable level_table(const Problem& P) {
+    LevelTable t{};
+    t.n_levels = P.n_levels;
+    for (int l = 0; l < P.n_levels; ++l) {
+        t.n[l] = P.lv[l].n;
+        t.basis[l] = P.lv[l].basis;
+        t.obs[l] = P.lv[l].obs_node;
+        t.S[l] = P.lv[l].dst_S;
+        t.lam[l] = P.lv[l].dst_lam;
+    }
+    return t;
+}
+
+// Host checks for a per-particle level map: 2D, and every grid served by the mixed-grid solve.
+static int check_levels(const Problem& P) {
+    if (P.dim != 2) return fail(SMC_E_INVAL, "level maps need the 2D problem");
+    for (int l = 0; l < P.n_levels; ++l)
+        if (!mixed_supported(P.lv[l].n))
+            return fail(SMC_E_INVAL, "grid %d cannot be mixed with others in one launch (64, 128, 256 can)",
+                        P.lv[l].n);
+    return SMC_OK;
+}
+
+static hipError_t forward_levels(smc_problem_s* ps, int prec, int64_t N, const double* xi, const Solve& o,
+                                 hipStream_t s) {
+    const Problem& P = ps->P;
+    const LevelTable lt = level_table(P);
+    hipError_t e = launch_synth2d_levels(xi, P.K, P.kl, P.sqrt_lam, lt, o.level, P.ws_e, P.e_stride, N, true, s);
+    if (e != hipSuccess) return e;
+    SolveArgs a = solve_args(P, 0);
+    a.G = o.G;
+    a.phi = o.phi;
+    a.iters = o.iters;
+    a.stats = P.profiling ? P.stats : nullptr;
+    const bool rec = P.profiling && !ps->capturing;
+    if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
+    const bool dst = prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO;
+    e = launch_solve_mixed(prec, dst, N, a, lt, o.level, P.ws_list, P.ws_counters, P.n_cu, s);
+    if (e != hipSuccess) return e;
+    if (rec) e = record(ps->pool, s);
+    return e;
+}
+
 static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, const Solve& o,
                           hipStream_t s) {
+    if (o.level) return forward_levels(ps, prec, N, xi, o, s);
     const Problem& P = ps->P;
     hipError_t e = synth(P, level, N, xi, P.ws_e, P.e_stride, true, s);
     if (e != hipSuccess) return e;
@@ -385,7 +441,8 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     a.fwd_given = o.w_given ? 1 : 0;
     a.lam = o.adjoint ? P.ws_lam : nullptr;
     a.stats = P.profiling ? P.stats : nullptr;
-    if (P.profiling && (e = record(ps->pool, s)) != hipSuccess) return e;
+    const bool rec = P.profiling && !ps->capturing;
+    if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
     if (P.dim == 1)
         e = launch_solve1d(L.n, N, a, s);
     else if (prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S)
@@ -393,7 +450,7 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     else
         e = launch_solve2d(L.n, prec, N, a, s);
     if (e != hipSuccess) return e;
-    if (P.profiling) e = record(ps->pool, s);
+    if (rec) e = record(ps->pool, s);
     return e;
 }
 
@@ -411,8 +468,13 @@ extern "C" int smc_forward_batch(smc_problem p, int64_t N, const double* xi, con
     if (int r = check_n(p->P, N)) return r;
     if (N > 0 && (!xi || !G)) return fail(SMC_E_INVAL, "xi and G must not be NULL");
     if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
-    if (level) return fail(SMC_E_INVAL, "per-particle level maps are not supported by this call; pass NULL");
+    if (level) {
+        if (int r = check_levels(p->P)) return r;
+        if (N > 0) HIPCHK(launch_plan(N, level, level_table(p->P), p->P.ws_list, p->P.ws_counters, p->P.flags,
+                                      (hipStream_t)stream));
+    }
     Solve o;
+    o.level = level;
     o.G = G;
     o.iters = iters;
     HIPCHK(forward(p, 0, prec, N, xi, o, (hipStream_t)stream));
@@ -465,36 +527,141 @@ extern "C" int smc_potential(smc_problem p, int64_t N, const double* G, double* 
     return SMC_OK;
 }
 
+// The move loop shared by smc_gmpcn_move and smc_gmpcn_stage (arguments already checked).
+static int move_loop(smc_problem_s* p, int64_t N, MoveParams q, int32_t n_moves, const int32_t* level, int32_t prec,
+                     double* xi, double* phi, int32_t* n_acc, hipStream_t s) {
+    const Problem& P = p->P;
+    if (N <= 0) return SMC_OK;
+    HIPCHK(launch_fill_i32(n_acc, N, 0, s));
+    if (level) HIPCHK(launch_plan(N, level, level_table(P), P.ws_list, P.ws_counters, P.flags, s));
+    for (int m = 0; m < n_moves; ++m) {
+        q.m = m;
+        HIPCHK(launch_propose(N, P.K, P.active, P.slot, q, xi, P.ws_v, P.ws_logr, P.flags, s));
+        Solve o;
+        o.level = level;
+        o.phi = P.ws_phinew;
+        o.iters = P.ws_iters;
+        HIPCHK(forward(p, 0, prec, N, P.ws_v, o, s));
+        HIPCHK(launch_accept(N, P.K, q, P.ws_v, P.ws_logr, P.ws_phinew, xi, phi, n_acc, s));
+    }
+    return SMC_OK;
+}
+
+static int check_move_common(const Problem& P, int64_t N, int32_t n_moves, const int32_t* level, int32_t prec,
+                             double* xi, double* phi, int32_t* n_acc) {
+    if (int r = check_n(P, N)) return r;
+    if (n_moves < 0) return fail(SMC_E_INVAL, "n_moves must be >= 0");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (level)
+        if (int r = check_levels(P)) return r;
+    if (N > 0 && (!xi || !phi || !n_acc)) return fail(SMC_E_INVAL, "xi, phi and n_acc must not be NULL");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    return SMC_OK;
+}
+
 extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
                               int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level, int32_t prec,
                               double* xi, double* phi, int32_t* n_acc, smc_stream stream) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
     const Problem& P = p->P;
-    if (int r = check_n(P, N)) return r;
     if (!gm) return fail(SMC_E_INVAL, "gm is NULL");
     if (gm->M < 1 || gm->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
     if (gm->kr != P.kr) return fail(SMC_E_INVAL, "gm.kr (%d) differs from the problem's kr (%d)", gm->kr, P.kr);
     if (!gm->logw || !gm->mean || !gm->scale) return fail(SMC_E_INVAL, "mixture arrays must not be NULL");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SMC_E_INVAL, "beta must be in (0, 1]");
     if (!(tau >= 0.0 && tau <= 1.0)) return fail(SMC_E_INVAL, "tau must be in [0, 1]");
-    if (n_moves < 0) return fail(SMC_E_INVAL, "n_moves must be >= 0");
-    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
-    if (level) return fail(SMC_E_INVAL, "per-particle level maps are not supported by this call; pass NULL");
-    if (N > 0 && (!xi || !phi || !n_acc)) return fail(SMC_E_INVAL, "xi, phi and n_acc must not be NULL");
-    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(launch_fill_i32(n_acc, N, 0, s));
-    for (int m = 0; m < n_moves; ++m) {
-        const uint64_t c = ctr + (uint64_t)m;
-        HIPCHK(launch_propose(N, P.K, P.kr, gm->M, P.active, P.slot, gm->logw, gm->mean, gm->scale, beta, seed, c,
-                              xi, P.ws_v, P.ws_logr, s));
-        Solve o;
-        o.phi = P.ws_phinew;
-        o.iters = P.ws_iters;
-        HIPCHK(forward(p, 0, prec, N, P.ws_v, o, s));
-        HIPCHK(launch_accept(N, P.K, tau, seed, c, P.ws_v, P.ws_logr, P.ws_phinew, xi, phi, n_acc, s));
-    }
+    if (int r = check_move_common(P, N, n_moves, level, prec, xi, phi, n_acc)) return r;
+    MoveParams q;
+    q.beta = beta;
+    q.tau = tau;
+    q.seed = seed;
+    q.ctr = ctr;
+    q.M = gm->M;
+    q.kr = gm->kr;
+    q.logw = gm->logw;
+    q.mean = gm->mean;
+    q.scale = gm->scale;
+    return move_loop(p, N, q, n_moves, level, prec, xi, phi, n_acc, (hipStream_t)stream);
+}
+
+static int stage_params(const Problem& P, const smc_stage* st, const int32_t* level, MoveParams& q) {
+    if (!st) return fail(SMC_E_INVAL, "stage is NULL");
+    const int G = level ? P.n_levels : 1;
+    if (st->n_groups != G)
+        return fail(SMC_E_INVAL, "n_groups (%d) must be %d (%s)", st->n_groups, G,
+                    level ? "the problem's grid count with a level map" : "1 without a level map");
+    if (st->M < 1 || st->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (st->kr != P.kr) return fail(SMC_E_INVAL, "kr (%d) differs from the problem's kr (%d)", st->kr, P.kr);
+    if (!st->logw || !st->mean || !st->scale || !st->beta || !st->tau || !st->ctr)
+        return fail(SMC_E_INVAL, "stage arrays must not be NULL");
+    q = MoveParams{};
+    q.seed = st->seed;
+    q.group = level;
+    q.beta_g = st->beta;
+    q.tau_g = st->tau;
+    q.ctr_dev = st->ctr;
+    q.n_groups = G;
+    q.M = st->M;
+    q.kr = st->kr;
+    q.logw = st->logw;
+    q.mean = st->mean;
+    q.scale = st->scale;
     return SMC_OK;
+}
+
+extern "C" int smc_gmpcn_stage(smc_problem p, int64_t N, const int32_t* level, const smc_stage* st, int32_t n_moves,
+                               int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    MoveParams q;
+    if (int r = stage_params(p->P, st, level, q)) return r;
+    if (int r = check_move_common(p->P, N, n_moves, level, prec, xi, phi, n_acc)) return r;
+    return move_loop(p, N, q, n_moves, level, prec, xi, phi, n_acc, (hipStream_t)stream);
+}
+
+extern "C" int smc_stage_graph_create(smc_problem p, int64_t N, const int32_t* level, const smc_stage* st,
+                                      int32_t n_moves, int32_t prec, double* xi, double* phi, int32_t* n_acc,
+                                      smc_stream stream, smc_graph* out) {
+    if (!p || !out) return fail(SMC_E_INVAL, "problem and out must not be NULL");
+    if (!stream) return fail(SMC_E_INVAL, "graph capture needs a created stream, not the null stream");
+    MoveParams q;
+    if (int r = stage_params(p->P, st, level, q)) return r;
+    if (int r = check_move_common(p->P, N, n_moves, level, prec, xi, phi, n_acc)) return r;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    p->capturing = true;
+    const int r = move_loop(p, N, q, n_moves, level, prec, xi, phi, n_acc, s);
+    p->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (r != SMC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (ec != hipSuccess) return fail(SMC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(SMC_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    smc_graph_s* gr = new smc_graph_s();
+    gr->graph = g;
+    gr->exec = ex;
+    *out = gr;
+    return SMC_OK;
+}
+
+extern "C" int smc_stage_graph_launch(smc_graph g, smc_stream stream) {
+    if (!g) return fail(SMC_E_INVAL, "graph is NULL");
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+extern "C" void smc_stage_graph_destroy(smc_graph g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 extern "C" int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, int32_t n_moves, uint64_t seed,

@@ -46,6 +46,9 @@ struct Problem {
     void* ws_vec = nullptr;      // [n_max][6][n_big^2] doubles: vectors of the global-memory solver
     double* ws_G = nullptr;      // [n_max][n_obs]
     int32_t* ws_iters = nullptr; // [n_max]
+    int32_t* ws_list = nullptr;  // [n_max] work list of a level map (particles grouped by grid)
+    unsigned long long* ws_counters = nullptr;   // [2] work and exit counters of the persistent solve
+    int n_cu = 0;                // compute units of the device
     int32_t* flags = nullptr;    // device status word
     unsigned long long* stats = nullptr;  // [4] iterations, sweeps, solves, preconditioner applications
     bool profiling = false;
@@ -101,7 +104,17 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Sum over the block in a fixed order; every thread gets the same bits.
+// A value every lane of the wave holds (read back from LDS, say) made visibly uniform to the
+// compiler: branches and loop exits on it are then compiled as wave-uniform, never as divergent
+// control flow around the barriers they enclose.
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the block in a fixed order; every thread gets the same bits (and the compiler knows).
 // `red` holds at least NW doubles of LDS; contains a barrier.
 template <int NW>
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -111,7 +124,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) s += red[w];
-    return s;
+    return uniform(s);
 }
 
 // ------------------------------------------------------------------ launchers (defined in k_*.hip)
@@ -138,6 +151,58 @@ struct SolveArgs {
     unsigned long long* stats;   // [4] iterations, sweeps, solves, preconditioner applications; or null
 };
 
+// Parameters of the moves of one call.  Either scalars for every particle, or per-group device
+// arrays, the group of particle n being group[n]; the counter of move m is ctr (or *ctr_dev) + m.
+// Mixture of group g: logw[g][M], mean[g][M][kr], scale[g][M][kr].
+struct MoveParams {
+    double beta = 0, tau = 0;
+    uint64_t seed = 0, ctr = 0;
+    const int32_t* group = nullptr;
+    const double* beta_g = nullptr;
+    const double* tau_g = nullptr;
+    const uint64_t* ctr_dev = nullptr;
+    int n_groups = 1;
+    int M = 1, kr = 0;
+    const double* logw = nullptr;
+    const double* mean = nullptr;
+    const double* scale = nullptr;
+    int m = 0;
+};
+
+// Group of particle n (-1 if out of range) and its parameters.
+__device__ __forceinline__ int mp_group(const MoveParams& q, int64_t n) {
+    if (!q.group) return 0;
+    const int g = q.group[n];
+    return (g >= 0 && g < q.n_groups) ? g : -1;
+}
+__device__ __forceinline__ double mp_beta(const MoveParams& q, int g) { return q.beta_g ? q.beta_g[g] : q.beta; }
+__device__ __forceinline__ double mp_tau(const MoveParams& q, int g) { return q.tau_g ? q.tau_g[g] : q.tau; }
+__device__ __forceinline__ uint64_t mp_ctr(const MoveParams& q) {
+    return (q.ctr_dev ? *q.ctr_dev : q.ctr) + (uint64_t)q.m;
+}
+__device__ __forceinline__ bool mp_valid(double beta, double tau) {
+    return beta > 0.0 && beta <= 1.0 && tau >= 0.0 && tau <= 1.0;
+}
+
+// Per-grid tables handed to the kernels that serve particles of several grids in one launch.
+struct LevelTable {
+    int n_levels;
+    int n[MAX_LEVELS];
+    const double* basis[MAX_LEVELS];
+    const int32_t* obs[MAX_LEVELS];
+    const void* S[MAX_LEVELS];       // bf16 sine transform, or null
+    const float* lam[MAX_LEVELS];
+};
+
+hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* sqrt_lam, const LevelTable& lt,
+                                 const int32_t* level, double* out, int64_t out_stride, int64_t N, bool exp_half,
+                                 hipStream_t s);
+bool mixed_supported(int n);
+hipError_t launch_plan(int64_t N, const int32_t* level, const LevelTable& lt, int32_t* list,
+                       unsigned long long* counters, int32_t* flags, hipStream_t s);
+hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a, const LevelTable& lt,
+                              const int32_t* level, const int32_t* list, unsigned long long* counters, int grid,
+                              hipStream_t s);
 hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_lam, const double* basis, int n,
                           double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
 hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, const double* basis, int n, double* out,
@@ -161,12 +226,11 @@ hipError_t launch_prior(int64_t N, int K, uint64_t seed, uint64_t ctr, double* x
 hipError_t launch_potential(int64_t N, int n_obs, const double* G, const double* y, double inv2s2, double* phi,
                             hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-hipError_t launch_propose(int64_t N, int K, int kr, int M, const int32_t* active, const int32_t* slot,
-                          const double* logw, const double* mean, const double* scale, double beta,
-                          uint64_t seed, uint64_t ctr, const double* xi, double* v, double* logr, hipStream_t s);
-hipError_t launch_accept(int64_t N, int K, double tau, uint64_t seed, uint64_t ctr, const double* v,
-                         const double* logr, const double* phinew, double* xi, double* phi, int32_t* n_acc,
-                         hipStream_t s);
+hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
+                          const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s);
+hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
+                         const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s);
+hipError_t prepare_kernels();
 hipError_t launch_gather(int64_t N, int K, const int32_t* idx, const double* xi_in, const double* phi_in,
                          double* xi_out, double* phi_out, hipStream_t s);
 hipError_t launch_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,

@@ -72,19 +72,33 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 // a sum over the active modes only (g = gamma).  The first argument of alpha is where the
 // reverse move lands.  This is the ratio of the Gaussian components' Radon-Nikodym
 // derivatives of eq. (auv of pCN-GMM4) written out for diagonal covariances.
-__global__ __launch_bounds__(256) void propose_kernel(int K, int kr, int M, const int32_t* __restrict__ active,
-                                                      const int32_t* __restrict__ slot,
-                                                      const double* __restrict__ logw,
-                                                      const double* __restrict__ mean,
-                                                      const double* __restrict__ scale, double beta,
-                                                      uint64_t seed, uint64_t ctr, const double* __restrict__ xi,
-                                                      double* __restrict__ v, double* __restrict__ logr) {
+__global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __restrict__ active,
+                                                      const int32_t* __restrict__ slot, MoveParams q,
+                                                      const double* __restrict__ xi, double* __restrict__ v,
+                                                      double* __restrict__ logr, int32_t* flags) {
     __shared__ int comp;
     __shared__ double fw[MAX_M], bw[MAX_M];
     const int64_t n = blockIdx.x;
+    const int grp = mp_group(q, n);
+    const double beta = grp >= 0 ? mp_beta(q, grp) : 0.0, tau = grp >= 0 ? mp_tau(q, grp) : 0.0;
+    const double* xp = xi + n * K;
+    double* vp = v + n * K;
+    if (grp < 0 || !mp_valid(beta, tau)) {   // no valid parameters: propose the current state, reject it
+        for (int k = threadIdx.x; k < K; k += 256) vp[k] = xp[k];
+        if (threadIdx.x == 0) {
+            logr[n] = -INFINITY;
+            if (grp >= 0 && flags) atomicOr(flags, SMC_FLAG_BADPARAM);
+        }
+        return;
+    }
+    const int M = q.M, kr = q.kr;
+    const double* logw = q.logw + (int64_t)grp * M;
+    const double* mean = q.mean + (int64_t)grp * M * kr;
+    const double* scale = q.scale + (int64_t)grp * M * kr;
+    const uint64_t ctr = mp_ctr(q);
     const double gamma = sqrt(1.0 - beta * beta);
     if (threadIdx.x == 0) {
-        const uint4 w = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const uint4 w = draw(q.seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
         const double uc = res53(w.x, w.y);
         double cum = 0.0;
         int j = M - 1;
@@ -96,12 +110,10 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, int kr, int M, cons
     }
     __syncthreads();
     const int j = comp;
-    const double* xp = xi + n * K;
-    double* vp = v + n * K;
     const int nb = (K + 1) / 2;
     for (int blk = threadIdx.x; blk < nb; blk += 256) {
         double z[2];
-        box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
+        box_muller(draw(q.seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int k = 2 * blk + h;
@@ -150,30 +162,29 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, int kr, int M, cons
     }
 }
 
-hipError_t launch_propose(int64_t N, int K, int kr, int M, const int32_t* active, const int32_t* slot,
-                          const double* logw, const double* mean, const double* scale, double beta,
-                          uint64_t seed, uint64_t ctr, const double* xi, double* v, double* logr, hipStream_t s) {
+hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
+                          const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    propose_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, kr, M, active, slot, logw, mean, scale, beta, seed,
-                                                           ctr, xi, v, logr);
+    propose_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
     return hipGetLastError();
 }
 
 // Metropolis-Hastings decision (Alg. 2): log a = min(0, tau (Phi(xi) - Phi(v)) + log R);
-// accept iff log U_acc < log a; a proposal without a finite potential is rejected.
-__global__ __launch_bounds__(256) void accept_kernel(int K, double tau, uint64_t seed, uint64_t ctr,
-                                                     const double* __restrict__ v, const double* __restrict__ logr,
+// accept iff log U_acc < log a; a proposal without a finite potential or log R is rejected.
+__global__ __launch_bounds__(256) void accept_kernel(int K, MoveParams q, const double* __restrict__ v,
+                                                     const double* __restrict__ logr,
                                                      const double* __restrict__ phinew, double* __restrict__ xi,
                                                      double* __restrict__ phi, int32_t* __restrict__ n_acc) {
     __shared__ int acc;
     const int64_t n = blockIdx.x;
     if (threadIdx.x == 0) {
-        const uint4 w = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const int grp = mp_group(q, n);
+        const uint4 w = draw(q.seed, mp_ctr(q), UNIFORM_BLOCK, (uint32_t)n);
         const double ua = res53(w.z, w.w);
-        const double pn = phinew[n];
+        const double pn = phinew[n], lr = logr[n];
         bool ok = false;
-        if (isfinite(pn)) {
-            const double la = fmin(0.0, tau * (phi[n] - pn) + logr[n]);
+        if (grp >= 0 && isfinite(pn) && lr > -INFINITY) {
+            const double la = fmin(0.0, mp_tau(q, grp) * (phi[n] - pn) + lr);
             ok = log(ua) < la;
         }
         acc = ok;
@@ -188,11 +199,10 @@ __global__ __launch_bounds__(256) void accept_kernel(int K, double tau, uint64_t
     }
 }
 
-hipError_t launch_accept(int64_t N, int K, double tau, uint64_t seed, uint64_t ctr, const double* v,
-                         const double* logr, const double* phinew, double* xi, double* phi, int32_t* n_acc,
-                         hipStream_t s) {
+hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
+                         const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    accept_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, tau, seed, ctr, v, logr, phinew, xi, phi, n_acc);
+    accept_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
     return hipGetLastError();
 }
 

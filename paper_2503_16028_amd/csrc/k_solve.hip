@@ -164,27 +164,45 @@ hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const vo
     return hipGetLastError();
 }
 
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// LDS bytes of the on-chip solver's big buffer: the exchange array, or the transform buffers.
+template <typename T, int NN, int R, bool DST>
+constexpr int onchip_smem() {
+    constexpr int NW = NN * NN / R / 64;
+    constexpr int XBYTES = (2 * (NN + 1) + NN * NN) * (int)sizeof(T);
+    return (DST && DstShape<NN, NW>::BYTES > XBYTES) ? DstShape<NN, NW>::BYTES : XBYTES;
+}
+
+// Small LDS of one solve: block-reduction slots and the adjoint's point sources.
+struct SolveShared {
+    double red1[16], red2[16];
+    double src_w[MAX_OBS];   // adjoint point sources: weight and unknown index (-1: none)
+    int src_at[MAX_OBS];
+};
+
+// One particle's solve by the whole workgroup (NN * NN / R threads); `smem` holds at least
+// onchip_smem<T, NN, R, DST>() bytes.  Used by the per-grid kernel and by the mixed-grid one.
 template <typename T, int NN, int R, bool DST, bool ADJ>
-__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf16* __restrict__ Stab,
-                                                         const float* __restrict__ lamtab) {
+__device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t row, const int32_t* __restrict__ obs,
+                                               unsigned char* smem, SolveShared& sh,
+                                               const __bf16* __restrict__ Stab, const float* __restrict__ lamtab) {
     constexpr int NT = NN * NN / R;
     constexpr int NW = NT / 64;
     constexpr int NP1 = NN + 1;
     constexpr int PAD = NN + 1;
     using DS = DstShape<NN, NW>;
-    constexpr int XBYTES = (2 * PAD + NN * NN) * (int)sizeof(T);
-    constexpr int SMEM = (DST && DS::BYTES > XBYTES) ? DS::BYTES : XBYTES;
     static_assert(!DST || (NN >= 32 && (DS::NB * DS::NB) % NW == 0 && NW % DS::NB == 0), "transform tiling");
-    __shared__ __align__(16) unsigned char smem[SMEM];
-    __shared__ double red1[NW], red2[NW];
-    __shared__ double src_w[MAX_OBS];   // adjoint point sources: weight and unknown index (-1: none)
-    __shared__ int src_at[MAX_OBS];
+    static_assert(NW <= 16, "reduction slots");
+    double* red1 = sh.red1;
+    double* red2 = sh.red2;
+    double* src_w = sh.src_w;
+    int* src_at = sh.src_at;
     T* ly = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = tid % NN, b = tid / NN;
     const int i = c + 1;
-    const int64_t row = blockIdx.x;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
     double* sd = a.sd + row * a.sd_stride;
@@ -243,7 +261,7 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
         __syncthreads();
         double val = 0.0;
         if (tid < a.n_obs) {
-            const int node = a.obs[tid];
+            const int node = obs[tid];
             const int jj = node / NP1, ii = node % NP1;
             const bool in = ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1;
             if (in) val = x64[(jj - 1) * NN + ii - 1];
@@ -446,21 +464,31 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
             atomicAdd(&a.stats[3], (unsigned long long)napp);
         }
     }
+    __syncthreads();   // the next body may reuse the LDS
+}
+
+template <typename T, int NN, int R, bool DST, bool ADJ>
+__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf16* __restrict__ Stab,
+                                                         const float* __restrict__ lamtab) {
+    __shared__ __align__(16) unsigned char smem[onchip_smem<T, NN, R, DST>()];
+    __shared__ SolveShared sh;
+    cg_onchip_body<T, NN, R, DST, ADJ>(a, blockIdx.x, a.obs, smem, sh, Stab, lamtab);
 }
 
 // Same method (Jacobi-scaled CG, product form) with every vector in global memory, for grids
 // whose vectors do not fit in one workgroup's registers and LDS; 1024 threads stride over
 // the nodes of one particle.
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
+__device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t row, const int NN,
+                                               const int32_t* __restrict__ obs, SolveShared& sh) {
     constexpr int NW = 16;
-    __shared__ double red1[NW], red2[NW];
-    __shared__ double src_w[MAX_OBS];
-    __shared__ int src_at[MAX_OBS];
+    double* red1 = sh.red1;
+    double* red2 = sh.red2;
+    double* src_w = sh.src_w;
+    int* src_at = sh.src_at;
     const int tid = threadIdx.x;
     const int NP1 = NN + 1;
     const int nodes = NN * NN;
-    const int64_t row = blockIdx.x;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
     double* sd = a.sd + row * a.sd_stride;
@@ -493,7 +521,7 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
         __syncthreads();
         double val = 0.0;
         if (tid < a.n_obs) {
-            const int node = a.obs[tid];
+            const int node = obs[tid];
             const int jj = node / NP1, ii = node % NP1;
             const bool in = ii >= 1 && ii <= NN - 1 && jj >= 1 && jj <= NN - 1;
             if (in) val = x64[(jj - 1) * NN + ii - 1];
@@ -621,6 +649,13 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
             atomicAdd(&a.stats[2], (unsigned long long)solves);
         }
     }
+    __syncthreads();
+}
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
+    __shared__ SolveShared sh;
+    cg_global_body<T, ADJ>(a, blockIdx.x, NN, a.obs, sh);
 }
 
 // 1D: the tridiagonal flux-form system has the closed-form solution
@@ -654,6 +689,161 @@ __global__ __launch_bounds__(256) void solve1d_kernel(SolveArgs a, int n, int64_
     }
     if (a.phi) a.phi[row] = s * a.inv2s2;
     if (a.iters) a.iters[row] = 0;
+}
+
+// ------------------------------------------------------------------ several grids in one launch
+// Particles on different grids (a per-particle level map) are solved by one persistent launch.
+// A work list orders the particles by grid, finest first, so the longest solves start first;
+// each workgroup of 1024 threads takes the next list entry from an atomic counter and runs the
+// solve body of that particle's grid until the list is exhausted.  The last workgroup to leave
+// zeroes the counters for the next launch.
+
+// Work list of a level map: particle ids grouped by grid (largest n first, then the lower level;
+// out-of-range levels last, with SMC_FLAG_BADLEVEL); zeroes the two counters.  One workgroup.
+__global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __restrict__ level, LevelTable lt,
+                                                    int32_t* __restrict__ list, unsigned long long* counters,
+                                                    int32_t* flags) {
+    __shared__ int wtot[16];
+    __shared__ int order[MAX_LEVELS + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        counters[0] = 0;
+        counters[1] = 0;
+        bool used[MAX_LEVELS] = {};
+        for (int r = 0; r < lt.n_levels; ++r) {
+            int best = -1;
+            for (int l = 0; l < lt.n_levels; ++l)
+                if (!used[l] && (best < 0 || lt.n[l] > lt.n[best])) best = l;
+            used[best] = true;
+            order[r] = best;
+        }
+        order[lt.n_levels] = -1;
+    }
+    __syncthreads();
+    int64_t base = 0;
+    bool bad = false;
+    for (int rank = 0; rank <= lt.n_levels; ++rank) {
+        const int target = order[rank];
+        for (int64_t c0 = 0; c0 < N; c0 += 1024) {
+            const int64_t p = c0 + tid;
+            bool f = false;
+            if (p < N) {
+                const int l = level[p];
+                f = (target >= 0) ? (l == target) : (l < 0 || l >= lt.n_levels);
+            }
+            const unsigned long long m = __ballot(f);
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wtot[wave] = __popcll(m);
+            __syncthreads();
+            int off = 0, tot = 0;
+            for (int w = 0; w < 16; ++w) {
+                off += (w < wave) ? wtot[w] : 0;
+                tot += wtot[w];
+            }
+            if (f) list[base + off + before] = (int32_t)p;
+            base += tot;
+            bad = bad || (target < 0 && tot > 0);
+            __syncthreads();
+        }
+    }
+    if (tid == 0 && bad && flags) atomicOr(flags, SMC_FLAG_BADLEVEL);
+}
+
+hipError_t launch_plan(int64_t N, const int32_t* level, const LevelTable& lt, int32_t* list,
+                       unsigned long long* counters, int32_t* flags, hipStream_t s) {
+    plan_kernel<<<dim3(1), dim3(1024), 0, s>>>(N, level, lt, list, counters, flags);
+    return hipGetLastError();
+}
+
+bool mixed_supported(int n) { return n == 64 || n == 128 || n == 256; }
+
+// Each grid's body as a separate function, so that each is register-allocated on its own (the
+// call happens once per particle).  The LDS they share is named directly, not passed by pointer,
+// so that the bodies keep their LDS instructions.
+constexpr int MIXED_SMEM = cmax(onchip_smem<float, 128, 16, true>(),
+                                cmax(onchip_smem<float, 64, 4, true>(), onchip_smem<double, 64, 4, false>()));
+__shared__ __align__(16) unsigned char g_mixed_smem[MIXED_SMEM];
+__shared__ SolveShared g_mixed_sh;
+
+template <typename T, int NN, int R, bool DST>
+__device__ __noinline__ void mixed_onchip(const SolveArgs& a, int64_t p, const int32_t* obs, const __bf16* S,
+                                          const float* lam) {
+    static_assert(onchip_smem<T, NN, R, DST>() <= MIXED_SMEM, "mixed-grid LDS");
+    cg_onchip_body<T, NN, R, DST, false>(a, p, obs, g_mixed_smem, g_mixed_sh, S, lam);
+}
+
+template <typename T>
+__device__ __noinline__ void mixed_global(const SolveArgs& a, int64_t p, int n, const int32_t* obs) {
+    cg_global_body<T, false>(a, p, n, obs, g_mixed_sh);
+}
+
+template <int PREC, bool DST>
+__global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTable lt,
+                                                           const int32_t* __restrict__ level,
+                                                           const int32_t* __restrict__ list, int64_t N,
+                                                           unsigned long long* counters) {
+    __shared__ unsigned long long item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&counters[0], 1ull);
+        __syncthreads();
+        // the item as a wave-uniform value: the loop exit and the grid dispatch below must compile
+        // as uniform branches, or the barriers in the loop would not be met by every lane alike
+        const int64_t item = __builtin_amdgcn_readfirstlane((int)(item_s < (unsigned long long)N ? item_s : N));
+        __syncthreads();
+        if (item >= N) break;
+        const int64_t p = __builtin_amdgcn_readfirstlane(list[item]);
+        const int l = __builtin_amdgcn_readfirstlane(level[p]);
+        const int n = (l >= 0 && l < lt.n_levels) ? lt.n[l] : 0;
+        const __bf16* S = n ? reinterpret_cast<const __bf16*>(lt.S[l]) : nullptr;
+        if constexpr (PREC == SMC_FP32_REFINE) {
+            if (n == 64)
+                mixed_onchip<float, 64, 4, DST>(a, p, lt.obs[l], S, lt.lam[l]);
+            else if (n == 128)
+                mixed_onchip<float, 128, 16, DST>(a, p, lt.obs[l], S, lt.lam[l]);
+            else if (n == 256)
+                mixed_global<float>(a, p, 256, lt.obs[l]);
+        } else {
+            if (n == 64)
+                mixed_onchip<double, 64, 4, false>(a, p, lt.obs[l], nullptr, nullptr);
+            else if (n == 128 || n == 256)
+                mixed_global<double>(a, p, n, lt.obs[l]);
+        }
+        if (n != 64 && n != 128 && n != 256) {   // no such grid: the particle is rejected
+            if (threadIdx.x < a.n_obs && a.G) a.G[p * a.n_obs + threadIdx.x] = NAN;
+            if (threadIdx.x == 0) {
+                if (a.phi) a.phi[p] = INFINITY;
+                if (a.iters) a.iters[p] = -1;
+            }
+        }
+        // every lane closes the iteration here, so that no thread-0-only region of this iteration
+        // can be merged with the next iteration's fetch by the compiler
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long done = atomicAdd(&counters[1], 1ull);
+        if (done == (unsigned long long)gridDim.x - 1ull) {   // every workgroup has stopped fetching
+            counters[0] = 0;
+            counters[1] = 0;
+        }
+    }
+}
+
+hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a, const LevelTable& lt,
+                              const int32_t* level, const int32_t* list, unsigned long long* counters, int grid,
+                              hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const unsigned g = (unsigned)(N < grid ? N : grid);
+    if (prec == SMC_FP32_REFINE) {
+        if (dst)
+            solve_mixed_kernel<SMC_FP32_REFINE, true><<<dim3(g), dim3(1024), 0, s>>>(a, lt, level, list, N, counters);
+        else
+            solve_mixed_kernel<SMC_FP32_REFINE, false><<<dim3(g), dim3(1024), 0, s>>>(a, lt, level, list, N, counters);
+    } else {
+        SolveArgs b = a;
+        b.tol_inner = 0.1 * a.tol64;
+        solve_mixed_kernel<SMC_FP64, false><<<dim3(g), dim3(1024), 0, s>>>(b, lt, level, list, N, counters);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int NN, int R, bool DST>

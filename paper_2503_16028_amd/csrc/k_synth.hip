@@ -16,19 +16,15 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 //   A[16][4]: lane = row + 16 * k     B[4][16]: lane = col + 16 * k
 //   D[16][16]: lane = col + 16 * (row % 4), element row / 4
 template <bool EXPHALF>
-__global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__ xi, int K, int kl,
-                                                      const double* __restrict__ sqrt_lam,
-                                                      const double* __restrict__ basis, int n,
-                                                      double* __restrict__ out, int64_t out_stride) {
-    extern __shared__ double smem[];
+__device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int kl, const double* __restrict__ sqrt_lam,
+                                             const double* __restrict__ basis, int n, double* __restrict__ op,
+                                             double* smem) {
     const int np1 = n + 1;
     const int npad = (np1 + 15) & ~15;
     constexpr int LD = KLP + 1;                 // padded row stride: conflict-free column reads
     double* X = smem;                           // [KLP][LD]
     double* Bs = X + KLP * LD;                  // [npad][LD]
     double* T = Bs + npad * LD;                 // [KLP][npad]
-    const int64_t p = blockIdx.x;
-    const double* xp = xi + p * K;
 
     for (int t = threadIdx.x; t < KLP * KLP; t += 256) {
         const int k = t / KLP, l = t % KLP;
@@ -58,7 +54,6 @@ __global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__
     }
     __syncthreads();
     // U[j][i] = sum_k T[k][j] B[i][k]
-    double* op = out + p * out_stride;
     for (int tile = wave; tile < ntj * ntj; tile += 4) {
         const int j0 = (tile / ntj) * 16, i0 = (tile % ntj) * 16;
         d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -75,6 +70,29 @@ __global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__
             if (i < np1 && j < np1) op[j * np1 + i] = EXPHALF ? exp(0.5 * acc[v]) : acc[v];
         }
     }
+}
+
+template <bool EXPHALF>
+__global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__ xi, int K, int kl,
+                                                      const double* __restrict__ sqrt_lam,
+                                                      const double* __restrict__ basis, int n,
+                                                      double* __restrict__ out, int64_t out_stride) {
+    extern __shared__ double smem[];
+    const int64_t p = blockIdx.x;
+    synth2d_body<EXPHALF>(xi + p * K, kl, sqrt_lam, basis, n, out + p * out_stride, smem);
+}
+
+// The same for particles on several grids: particle p on grid level[p] (others are skipped).
+template <bool EXPHALF>
+__global__ __launch_bounds__(256) void synth2d_levels_kernel(const double* __restrict__ xi, int K, int kl,
+                                                             const double* __restrict__ sqrt_lam, LevelTable lt,
+                                                             const int32_t* __restrict__ level,
+                                                             double* __restrict__ out, int64_t out_stride) {
+    extern __shared__ double smem[];
+    const int64_t p = blockIdx.x;
+    const int l = level[p];
+    if (l < 0 || l >= lt.n_levels) return;
+    synth2d_body<EXPHALF>(xi + p * K, kl, sqrt_lam, lt.basis[l], lt.n[l], out + p * out_stride, smem);
 }
 
 // 1D: u[i] = sum_k S[i][k] sqrt(lambda_k) xi_k with S[i][k] = sqrt(2) sin(k pi i / n).
@@ -183,9 +201,6 @@ hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w
     if (N <= 0) return hipSuccess;
     const int ipad = (n + 1 + 3) & ~3;
     const size_t lds = sizeof(double) * (32 * (size_t)(ipad + 1) + 32 * (size_t)(KLP + 1));
-    hipError_t r = hipFuncSetAttribute((const void*)gradsynth2d_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (r != hipSuccess) return r;
     gradsynth2d_kernel<<<dim3((unsigned)N), dim3(256), lds, s>>>(e, e_stride, w, w_stride, lam, lam_stride, iters,
                                                                  sqrt_lam, basis, n, kl, K, grad);
     return hipGetLastError();
@@ -196,18 +211,45 @@ hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_la
     if (N <= 0) return hipSuccess;
     const int npad = (n + 1 + 15) & ~15;
     const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)npad * (KLP + 1) + (size_t)KLP * npad);
-    if (exp_half) {
-        hipError_t e = hipFuncSetAttribute((const void*)synth2d_kernel<true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    if (exp_half)
         synth2d_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void*)synth2d_kernel<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    else
         synth2d_kernel<false><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
-    }
     return hipGetLastError();
+}
+
+hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* sqrt_lam, const LevelTable& lt,
+                                 const int32_t* level, double* out, int64_t out_stride, int64_t N, bool exp_half,
+                                 hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    int nmax = 0;
+    for (int l = 0; l < lt.n_levels; ++l) nmax = lt.n[l] > nmax ? lt.n[l] : nmax;
+    const int npad = (nmax + 1 + 15) & ~15;
+    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)npad * (KLP + 1) + (size_t)KLP * npad);
+    if (exp_half)
+        synth2d_levels_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
+                                                                             out_stride);
+    else
+        synth2d_levels_kernel<false><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
+                                                                              out_stride);
+    return hipGetLastError();
+}
+
+// Dynamic LDS limits of the synthesis kernels, set once for the largest grid (256 intervals), so
+// that no launch needs an attribute call (launches may be captured into graphs).
+hipError_t prepare_kernels() {
+    constexpr int npad = (256 + 1 + 15) & ~15, ipad = (256 + 1 + 3) & ~3;
+    const int synth = (int)sizeof(double) * (KLP * (KLP + 1) + npad * (KLP + 1) + KLP * npad);
+    const int grad = (int)sizeof(double) * (32 * (ipad + 1) + 32 * (KLP + 1));
+    const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
+    hipError_t e = hipSuccess;
+    auto ck = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    ck(hipFuncSetAttribute((const void*)synth2d_kernel<true>, A, synth));
+    ck(hipFuncSetAttribute((const void*)synth2d_kernel<false>, A, synth));
+    ck(hipFuncSetAttribute((const void*)synth2d_levels_kernel<true>, A, synth));
+    ck(hipFuncSetAttribute((const void*)synth2d_levels_kernel<false>, A, synth));
+    ck(hipFuncSetAttribute((const void*)gradsynth2d_kernel, A, grad));
+    return e;
 }
 
 hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, const double* basis, int n, double* out,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libsmc.so")
 SMC_OK = 0
 SMC_FP64 = 0
 SMC_FP32_REFINE = 1
-FLAG_NOCONV, FLAG_STALL, FLAG_NONFINITE, FLAG_BADWEIGHTS = 1, 2, 4, 8
+FLAG_NOCONV, FLAG_STALL, FLAG_NONFINITE, FLAG_BADWEIGHTS, FLAG_BADLEVEL, FLAG_BADPARAM = 1, 2, 4, 8, 16, 32
 PRECISIONS = {"fp64": SMC_FP64, "fp32_refine": SMC_FP32_REFINE}
 PRECOND_AUTO, PRECOND_JACOBI = 0, 1
 
@@ -41,6 +41,11 @@ class GMDesc(ctypes.Structure):
     _fields_ = [("M", c_i32), ("kr", c_i32), ("logw", c_vp), ("mean", c_vp), ("scale", c_vp)]
 
 
+class StageDesc(ctypes.Structure):
+    _fields_ = [("n_groups", c_i32), ("M", c_i32), ("kr", c_i32), ("logw", c_vp), ("mean", c_vp), ("scale", c_vp),
+                ("beta", c_vp), ("tau", c_vp), ("ctr", c_vp), ("seed", c_u64)]
+
+
 _SIGS = {
     "smc_problem_create": (c_i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(c_vp)]),
     "smc_problem_destroy": (None, [c_vp]),
@@ -56,6 +61,11 @@ _SIGS = {
     "smc_forward_state": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_value_and_grad": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_pcnl_move": (c_i32, [c_vp, c_i64, c_dbl, c_dbl, c_i32, c_u64, c_u64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "smc_gmpcn_stage": (c_i32, [c_vp, c_i64, c_vp, ctypes.POINTER(StageDesc), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "smc_stage_graph_create": (c_i32, [c_vp, c_i64, c_vp, ctypes.POINTER(StageDesc), c_i32, c_i32, c_vp, c_vp, c_vp,
+                                       c_vp, ctypes.POINTER(c_vp)]),
+    "smc_stage_graph_launch": (c_i32, [c_vp, c_vp]),
+    "smc_stage_graph_destroy": (None, [c_vp]),
     "smc_temper": (c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_resample": (c_i32, [c_i64, c_vp, c_u64, c_vp, c_vp, c_vp]),
     "smc_gather": (c_i32, [c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -200,6 +210,7 @@ def gm_desc(logw, mean, scale):
     d.logw = _ptr(logw, torch.float64, M, "logw")
     d.mean = _ptr(mean, torch.float64, M * kr, "mean")
     d.scale = _ptr(scale, torch.float64, M * kr, "scale")
+    d._tensors = (logw, mean, scale)
     return d
 
 
@@ -236,6 +247,59 @@ def smc_pcnl_move(problem, N, beta, tau, n_moves, seed, ctr, prec, xi, phi, grad
                                _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
                                _ptr(grad, torch.float64, N * problem.K, "grad"), _ptr(n_acc, torch.int32, N, "n_acc"),
                                _stream(stream)))
+
+
+def stage_desc(n_groups, logw, mean, scale, beta, tau, ctr, seed):
+    """Device tensors: logw [G][M], mean and scale [G][M][kr], beta [G], tau [G], ctr [1] (int64)."""
+    M = logw.shape[-1]
+    kr = mean.shape[-1]
+    d = StageDesc()
+    d.n_groups, d.M, d.kr, d.seed = int(n_groups), M, kr, int(seed)
+    d.logw = _ptr(logw, torch.float64, n_groups * M, "logw")
+    d.mean = _ptr(mean, torch.float64, n_groups * M * kr, "mean")
+    d.scale = _ptr(scale, torch.float64, n_groups * M * kr, "scale")
+    d.beta = _ptr(beta, torch.float64, n_groups, "beta")
+    d.tau = _ptr(tau, torch.float64, n_groups, "tau")
+    d.ctr = _ptr(ctr, torch.int64, 1, "ctr")
+    # the descriptor holds device addresses: keep the tensors alive as long as it (and any graph
+    # captured from it) exists, or their memory could be reused before the kernels read it
+    d._tensors = (logw, mean, scale, beta, tau, ctr)
+    return d
+
+
+def smc_gmpcn_stage(problem, N, level, stage, n_moves, prec, xi, phi, n_acc, stream=None):
+    """stage: a StageDesc from stage_desc(...)."""
+    _check(lib().smc_gmpcn_stage(problem.handle, N, _ptr(level, torch.int32, N, "level", optional=True),
+                                 ctypes.byref(stage), int(n_moves), prec, _ptr(xi, torch.float64, N * problem.K, "xi"),
+                                 _ptr(phi, torch.float64, N, "phi"), _ptr(n_acc, torch.int32, N, "n_acc"),
+                                 _stream(stream)))
+
+
+class StageGraph:
+    """smc_gmpcn_stage captured once into a HIP graph; launch() replays it."""
+
+    def __init__(self, problem, N, level, stage, n_moves, prec, xi, phi, n_acc, stream):
+        self.handle = c_vp()
+        self._keep = (problem, level, stage, xi, phi, n_acc)
+        _check(lib().smc_stage_graph_create(problem.handle, N, _ptr(level, torch.int32, N, "level", optional=True),
+                                            ctypes.byref(stage), int(n_moves), prec,
+                                            _ptr(xi, torch.float64, N * problem.K, "xi"),
+                                            _ptr(phi, torch.float64, N, "phi"), _ptr(n_acc, torch.int32, N, "n_acc"),
+                                            _stream(stream), ctypes.byref(self.handle)))
+
+    def launch(self, stream=None):
+        _check(lib().smc_stage_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().smc_stage_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def smc_temper(N, phi, tau_in, ess_frac, h, tau_new, W, log_z_inc, flags=None, stream=None):

@@ -1,0 +1,252 @@
+"""Particles on several grids in one launch (level maps), per-group stage parameters and the
+captured stage graph, against the oracle and against the single-grid calls (GPU).
+
+Tolerances as in the single-grid parity tests: FP64 1e-10 relative, FP32+refinement 1e-7 on G
+and 1e-4 on potentials; accept counts bit-exact; graph replays bit-identical to eager runs.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from conftest import golden
+from oracle.forward import observe, phi as oracle_phi, solve
+from oracle.moves import GM, gmpcn_moves
+from oracle.problem import Problem as OProblem, synthesize
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+GRIDS = [64, 128, 256]
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    d = json.load(open(golden("problem_%s.json" % name)))
+    return d, OProblem(d)
+
+
+def t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2503_16028_amd import smc
+    smc.lib()
+    assert torch.cuda.is_available()
+
+
+def mixed_problem(d, N, prec_name, **kw):
+    from paper_2503_16028_amd import smc
+    if prec_name == "fp64":
+        return smc.Problem(d, N, grids=GRIDS, tol64=6e-12, max_iter=60 * 256, max_sweeps=6, **kw)
+    return smc.Problem(d, N, grids=GRIDS, tol64=1e-10, tol_inner=1e-5, max_iter=80 * 256, **kw)
+
+
+LEVELS = np.array([2, 1, 0, 0, 1, 0, 1, 0], dtype=np.int32)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32_refine"])
+def test_forward_levels(prec_name):
+    """One launch over 64^2, 128^2 and 256^2 particles; each row equals the oracle on its grid,
+    and the 128^2 and 256^2 rows equal, bit for bit, the single-grid launch (same solver body)."""
+    from paper_2503_16028_amd import smc
+    banner("forward levels", prec_name)
+    d, op = load("c5")
+    N = len(LEVELS)
+    prec = smc.PRECISIONS[prec_name]
+    p = mixed_problem(d, N, prec_name)
+    xi = inputs.particles(N, op.K, 40)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), t(LEVELS, torch.int32), prec, G, it)
+    torch.cuda.synchronize()
+    got = G.cpu().numpy()
+    assert (it.cpu().numpy() > 0).all()
+    assert smc.smc_status_flags(p) == 0
+    tol = 1e-10 if prec_name == "fp64" else 1e-7
+    for k in range(N):
+        n = GRIDS[LEVELS[k]]
+        ref = observe(op, solve(op, synthesize(op, xi[k], n), n), n)
+        assert np.abs(got[k] - ref).max() <= tol * np.abs(ref).max(), (k, n)
+    for lv in (1, 2):
+        rows = np.nonzero(LEVELS == lv)[0]
+        q = smc.Problem(d, len(rows), grids=[GRIDS[lv]], tol64=p_tol(prec_name), tol_inner=1e-5,
+                        max_iter=(60 if prec_name == "fp64" else 80) * 256, max_sweeps=6 if prec_name == "fp64" else 8)
+        G1 = torch.empty(len(rows), op.n_obs, dtype=torch.float64, device=DEV)
+        smc.smc_forward_batch(q, len(rows), t(xi[rows]), None, prec, G1)
+        torch.cuda.synchronize()
+        assert np.array_equal(G1.cpu().numpy(), got[rows]), lv
+
+
+def p_tol(prec_name):
+    return 6e-12 if prec_name == "fp64" else 1e-10
+
+
+def test_forward_levels_out_of_range():
+    from paper_2503_16028_amd import smc
+    banner("forward levels out of range")
+    d, op = load("c5")
+    lv = np.array([0, 5, -1, 1], dtype=np.int32)
+    N = len(lv)
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 41)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), t(lv, torch.int32), smc.SMC_FP32_REFINE, G, it)
+    torch.cuda.synchronize()
+    g, i = G.cpu().numpy(), it.cpu().numpy()
+    assert np.isnan(g[1]).all() and np.isnan(g[2]).all() and i[1] == -1 and i[2] == -1
+    assert np.isfinite(g[0]).all() and np.isfinite(g[3]).all() and i[0] > 0 and i[3] > 0
+    assert smc.smc_status_flags(p) & smc.FLAG_BADLEVEL
+
+
+def group_mixture(op, G, M, seed):
+    logw, mean, scale = [], [], []
+    for g in range(G):
+        lw, mu, sc = inputs.mixture(M, op.kr, seed + g, spread=0.5)
+        logw.append(lw), mean.append(mu), scale.append(sc)
+    return np.array(logw), np.array(mean), np.array(scale)
+
+
+def test_stage_per_group_matches_oracle():
+    """Three samplers (one per grid), each with its own mixture, beta and tau, moved in one
+    call; every particle replays the oracle's moves on its grid with its group's parameters."""
+    from paper_2503_16028_amd import smc
+    banner("stage per group fp64")
+    d, op = load("c5")
+    lv = np.array([0, 1, 0, 2, 1, 0], dtype=np.int32)
+    N, M, n_moves, seed, ctr = len(lv), 3, 2, 31, 5000
+    p = mixed_problem(d, N, "fp64")
+    xi = inputs.particles(N, op.K, 42) * 0.3
+    logw, mean, scale = group_mixture(op, 3, M, 43)
+    beta = np.array([0.3, 0.2, 0.4])
+    tau = np.array([1e-3, 2e-3, 5e-4])
+    X, L = t(xi), t(lv, torch.int32)
+    Gm = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, X, L, smc.SMC_FP64, Gm)
+    smc.smc_potential(p, N, Gm, phi)
+    acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    ctr_t = torch.tensor([ctr], dtype=torch.int64, device=DEV)
+    tens = [t(logw), t(mean), t(scale), t(beta), t(tau)]
+    sd = smc.stage_desc(3, *tens, ctr_t, seed)
+    smc.smc_gmpcn_stage(p, N, L, sd, n_moves, smc.SMC_FP64, X, phi, acc)
+    torch.cuda.synchronize()
+    gx, gphi, gacc = X.cpu().numpy(), phi.cpu().numpy(), acc.cpu().numpy()
+    assert smc.smc_status_flags(p) == 0
+    for g in range(3):
+        ids = np.nonzero(lv == g)[0]
+        n = GRIDS[g]
+        gm = GM(logw[g], mean[g], scale[g], op.active(), op.K)
+        ph0 = np.array([oracle_phi(op, x, n) for x in xi[ids]])
+        rx, rphi, racc = gmpcn_moves(op, n, xi[ids], ph0, gm, beta[g], tau[g], n_moves, seed, ctr, ids=ids)
+        assert np.array_equal(gacc[ids], racc), (g, gacc[ids], racc)
+        assert np.abs(gx[ids] - rx).max() <= 1e-10 * np.abs(rx).max()
+        assert np.abs(gphi[ids] / rphi - 1).max() <= 1e-9
+    assert 0 < gacc.sum() < N * n_moves
+
+
+def test_stage_equals_scalar_move_with_levels():
+    """Equal parameters in every group: smc_gmpcn_stage and smc_gmpcn_move with the same level
+    map produce the same bits."""
+    from paper_2503_16028_amd import smc
+    banner("stage vs scalar move")
+    d, op = load("c5")
+    lv = np.array([1, 0, 0, 1, 0, 0, 1, 0, 0, 0], dtype=np.int32)
+    N, M = len(lv), 2
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 44) * 0.3
+    lw, mu, sc = inputs.mixture(M, op.kr, 45, spread=0.5)
+    L = t(lv, torch.int32)
+    Gm = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    phi0 = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), L, smc.SMC_FP32_REFINE, Gm)
+    smc.smc_potential(p, N, Gm, phi0)
+    Xa, Pa, Aa = t(xi), phi0.clone(), torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_gmpcn_move(p, N, (t(lw), t(mu), t(sc)), 0.3, 2e-3, 3, 9, 700, L, smc.SMC_FP32_REFINE, Xa, Pa, Aa)
+    Xb, Pb, Ab = t(xi), phi0.clone(), torch.empty(N, dtype=torch.int32, device=DEV)
+    G3 = 3
+    sd = smc.stage_desc(G3, t(np.tile(lw, (G3, 1))), t(np.tile(mu, (G3, 1, 1))), t(np.tile(sc, (G3, 1, 1))),
+                        t(np.full(G3, 0.3)), t(np.full(G3, 2e-3)), torch.tensor([700], dtype=torch.int64, device=DEV),
+                        9)
+    smc.smc_gmpcn_stage(p, N, L, sd, 3, smc.SMC_FP32_REFINE, Xb, Pb, Ab)
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb) and torch.equal(Pa, Pb) and torch.equal(Aa, Ab)
+    assert 0 < Aa.sum().item()
+
+
+def test_stage_bad_parameters_keep_state():
+    from paper_2503_16028_amd import smc
+    banner("stage bad parameters")
+    d, op = load("c5")
+    lv = np.array([0, 1, 0, 0], dtype=np.int32)
+    N, M = len(lv), 1
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 46) * 0.3
+    L = t(lv, torch.int32)
+    phi = torch.zeros(N, dtype=torch.float64, device=DEV)
+    X = t(xi)
+    acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    sd = smc.stage_desc(3, t(np.zeros((3, M))), t(np.zeros((3, M, op.kr))), t(np.ones((3, M, op.kr))),
+                        t([0.5, 1.5, 0.5]), t([0.0, 0.0, 0.0]), torch.tensor([0], dtype=torch.int64, device=DEV), 1)
+    smc.smc_gmpcn_stage(p, N, L, sd, 2, smc.SMC_FP32_REFINE, X, phi, acc)
+    torch.cuda.synchronize()
+    a = acc.cpu().numpy()
+    assert a[1] == 0 and np.array_equal(X.cpu().numpy()[1], xi[1])
+    assert (a[[0, 2, 3]] == 2).all()            # tau = 0 and Phi = 0: plain pCN accepts every move
+    assert smc.smc_status_flags(p) & smc.FLAG_BADPARAM
+
+
+def test_stage_graph_replays_match_eager():
+    """The captured stage replayed three times, with tau, beta and the counter changed on the
+    device between replays and eager work in between; each replay equals an eager run from the
+    same state, bit for bit."""
+    from paper_2503_16028_amd import smc
+    banner("stage graph replay")
+    d, op = load("c5")
+    lv = np.array([1, 0, 0, 1, 0, 0, 0, 1], dtype=np.int32)
+    N, M, n_moves = len(lv), 2, 2
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 47) * 0.3
+    logw, mean, scale = group_mixture(op, 3, M, 48)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        L = t(lv, torch.int32)
+        Xg = t(xi)
+        Gm = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+        Pg = torch.empty(N, dtype=torch.float64, device=DEV)
+        smc.smc_forward_batch(p, N, Xg, L, smc.SMC_FP32_REFINE, Gm)
+        smc.smc_potential(p, N, Gm, Pg)
+        Ag = torch.empty(N, dtype=torch.int32, device=DEV)
+        beta = t([0.3, 0.25, 0.3])
+        tau = t([1e-3, 1e-3, 1e-3])
+        ctr = torch.tensor([100], dtype=torch.int64, device=DEV)
+        sd = smc.stage_desc(3, t(logw), t(mean), t(scale), beta, tau, ctr, 77)
+        s.synchronize()
+        graph = smc.StageGraph(p, N, L, sd, n_moves, smc.SMC_FP32_REFINE, Xg, Pg, Ag, s)
+        Xr = torch.empty_like(Xg)
+        Pr = torch.empty_like(Pg)
+        Ar = torch.empty_like(Ag)
+        total = 0
+        for rep in range(3):
+            tau.mul_(2.0)
+            beta.sub_(0.05)
+            ctr.add_(1 << 20)
+            Xr.copy_(Xg)
+            Pr.copy_(Pg)
+            smc.smc_gmpcn_stage(p, N, L, sd, n_moves, smc.SMC_FP32_REFINE, Xr, Pr, Ar, s)
+            graph.launch(s)
+            s.synchronize()
+            assert torch.equal(Xg, Xr) and torch.equal(Pg, Pr) and torch.equal(Ag, Ar), rep
+            total += int(Ag.sum().item())
+        graph.close()
+    assert total > 0
+    assert smc.smc_status_flags(p) == 0
