@@ -62,6 +62,77 @@ def _oracle_chunk(args):
     return n, time.perf_counter() - t0
 
 
+def pcnl_variant(dev, N=2048, n_moves=20):
+    """pCN-Langevin moves at 128^2 (each proposal: forward and adjoint solves, gradient synthesis)."""
+    import numpy as np
+    import torch
+    from paper_2503_16028_amd import smc
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_c4.json")))
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-5)
+    xi = torch.empty(N, p.K, dtype=torch.float64, device=dev)
+    smc.smc_prior_sample(p, N, 2503, 0, xi)
+    xi.mul_(0.5)
+    phi = torch.empty(N, dtype=torch.float64, device=dev)
+    g = torch.empty(N, p.K, dtype=torch.float64, device=dev)
+    acc = torch.empty(N, dtype=torch.int32, device=dev)
+    smc.smc_value_and_grad(p, N, xi, smc.SMC_FP32_REFINE, None, phi, g)
+    tau = float(min(1.0, 2.0 / phi.median().item()))
+    smc.smc_pcnl_move(p, N, 0.2, tau, 1, 7, 1, smc.SMC_FP32_REFINE, xi, phi, g, acc)   # warm-up
+    torch.cuda.synchronize()
+    smc.smc_profile(p, 1)
+    t0 = time.perf_counter()
+    smc.smc_pcnl_move(p, N, 0.2, tau, n_moves, 7, 100, smc.SMC_FP32_REFINE, xi, phi, g, acc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pr = smc.smc_profile_read(p)
+    smc.smc_profile(p, 0)
+    return {"pcnl_128_N2048_moves_per_s": N * n_moves / dt,
+            "pcnl_accept_rate": float(acc.sum().item()) / (N * n_moves),
+            "pcnl_solve_ms_per_launch": pr["ms"] / max(1, pr["launches"]),
+            "pcnl_cg_iters_per_solve": pr["iters"] / max(1, pr["solves"])}
+
+
+def mixed_variant(dev, counts=(4096, 3072, 1024), n_moves=20, stages=2):
+    """Three samplers on 64^2, 128^2 and 256^2 (N = 8192) moved by one captured stage graph."""
+    import numpy as np
+    import torch
+    from paper_2503_16028_amd import smc
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_c5.json")))
+    N = sum(counts)
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-5)
+    level = torch.cat([torch.full((c,), l, dtype=torch.int32) for l, c in enumerate(counts)]).to(dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        xi = torch.empty(N, p.K, dtype=torch.float64, device=dev)
+        smc.smc_prior_sample(p, N, 2503, 0, xi)
+        G = torch.empty(N, p.n_obs, dtype=torch.float64, device=dev)
+        phi = torch.empty(N, dtype=torch.float64, device=dev)
+        smc.smc_forward_batch(p, N, xi, level, smc.SMC_FP32_REFINE, G)
+        smc.smc_potential(p, N, G, phi)
+        M, kr = 8, p.kr
+        logw = torch.full((3, M), -float(np.log(M)), dtype=torch.float64, device=dev)
+        mean = torch.zeros(3, M, kr, dtype=torch.float64, device=dev)
+        scale = torch.ones(3, M, kr, dtype=torch.float64, device=dev)
+        beta = torch.full((3,), 0.2, dtype=torch.float64, device=dev)
+        tau = torch.full((3,), 1e-4, dtype=torch.float64, device=dev)
+        ctr = torch.zeros(1, dtype=torch.int64, device=dev)
+        acc = torch.empty(N, dtype=torch.int32, device=dev)
+        sd = smc.stage_desc(3, logw, mean, scale, beta, tau, ctr, 11)
+        graph = smc.StageGraph(p, N, level, sd, n_moves, smc.SMC_FP32_REFINE, xi, phi, acc, s)
+        graph.launch(s)                       # warm-up stage
+        s.synchronize()
+        t0 = time.perf_counter()
+        for k in range(stages):
+            ctr.add_(1 << 20)
+            graph.launch(s)
+        s.synchronize()
+        dt = time.perf_counter() - t0
+        graph.close()
+    return {"mixed_64_128_256_N8192_moves_per_s": N * n_moves * stages / dt,
+            "mixed_stage_ms": 1e3 * dt / stages,
+            "mixed_counts": list(counts)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +214,8 @@ def main():
     achieved = mfma_flops / (prof32["ms"] * 1e-3)
     variants = {}
     if not args.no_variants:
+        variants.update(pcnl_variant(dev))
+        variants.update(mixed_variant(dev))
         t64, prof64, _ = stage_loop(smc.SMC_FP64, 1, 0, 4)
         variants["fp64_batched_moves_per_s"] = N * 4 / t64
         variants["fp64_batched_solve_ms_per_launch"] = prof64["ms"] / max(1, prof64["launches"])

@@ -248,7 +248,7 @@ int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
  * grids, z = L^{-1} r with L the constant-coefficient Dirichlet Laplacian of grid `level`, up
  * to a positive constant factor, computed with bf16 sine transforms on the matrix cores.
  * r, z: [N][n][n] FP32, element [g][c] for the node ((c+1)/n, (g+1)/n); index n-1 is boundary
- * padding and must hold 0 in r.  Only grids of 32, 64 and 128 intervals. */
+ * padding and must hold 0 in r.  Grids of 32, 64, 128 and 256 intervals. */
 int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z, smc_stream stream);
 
 /* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by

@@ -151,11 +151,16 @@ __global__ __launch_bounds__(NN * NN / R) void dst_apply_kernel(const float* __r
     for (int k = 0; k < R; ++k) zout[base + (b * R + k) * NN + c] = Z[(b * R + k) * DstShape<NN, NW>::LDZ + c];
 }
 
+__global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
+                                                            const __bf16* __restrict__ Stab,
+                                                            const float* __restrict__ lamtab);
+
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
                             hipStream_t s) {
     if (N <= 0) return hipSuccess;
     const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
     switch (n) {
+        case 256: dst256_apply_kernel<<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
         case 32: dst_apply_kernel<32, 4><<<dim3((unsigned)N), dim3(256), 0, s>>>(r, z, Sb, lam); break;
         case 64: dst_apply_kernel<64, 8><<<dim3((unsigned)N), dim3(512), 0, s>>>(r, z, Sb, lam); break;
         case 128: dst_apply_kernel<128, 16><<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
@@ -478,10 +483,84 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
 // Same method (Jacobi-scaled CG, product form) with every vector in global memory, for grids
 // whose vectors do not fit in one workgroup's registers and LDS; 1024 threads stride over
 // the nodes of one particle.
-template <typename T, bool ADJ>
+// The fast-Poisson preconditioner z = L^{-1} r of a 256 x 256 grid whose vectors live in global
+// memory (one workgroup of 16 waves).  L^{-1} = S diag(1 / (lam_i + lam_j)) S is applied as four
+// passes X <- (X S)^T over a single bf16 copy of the grid in LDS: each pass is a batch of
+// independent 1D sine transforms along the rows, and the transposed write-back turns the next pass
+// into the transform along the other axis.  Wave w owns output columns 16w..16w+15, keeps its
+// 16-column slice of S in registers, holds its 16 result tiles until every wave has read X, then
+// writes them transposed.  The second pass applies 1 / (lam_i + lam_j); the fourth writes z (FP32).
+constexpr int D256_LD = 256 + 8;
+constexpr int D256_BYTES = 256 * D256_LD * 2;
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, __bf16* X,
+                                             const __bf16* __restrict__ S, const float* __restrict__ lam) {
+    constexpr int NN = 256, LD = D256_LD, KS = 8, NB = 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4, cb = wave;
+    bf8 sB[KS];   // B operand: S[k][16 cb + lr] = S[16 cb + lr][k] (S is symmetric)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) sB[ks] = *reinterpret_cast<const bf8*>(S + (16 * cb + lr) * NN + 32 * ks + 8 * lk);
+    for (int e = tid; e < NN * NN / 8; e += 1024) {   // X = bf16(r), row-major
+        const int g = e >> 5, c0 = (e & 31) * 8;
+        const float4 u0 = *reinterpret_cast<const float4*>(r + g * NN + c0);
+        const float4 u1 = *reinterpret_cast<const float4*>(r + g * NN + c0 + 4);
+        bf8 v;
+        v[0] = (__bf16)u0.x; v[1] = (__bf16)u0.y; v[2] = (__bf16)u0.z; v[3] = (__bf16)u0.w;
+        v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
+        *reinterpret_cast<bf8*>(X + g * LD + c0) = v;
+    }
+    __syncthreads();
+    const float lam_c = lam[16 * cb + lr];
+#pragma unroll 1
+    for (int step = 0; step < 4; ++step) {
+        bf4 out[NB];
+#pragma unroll
+        for (int ra = 0; ra < NB; ++ra) {   // P[i][j] = sum_k X[i][k] S[k][j], i in row tile ra, j in cb
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc = mfma_bf16(*reinterpret_cast<const bf8*>(X + (16 * ra + lr) * LD + 32 * ks + 8 * lk), sB[ks], acc);
+            if (step == 1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] *= __builtin_amdgcn_rcpf(lam[16 * ra + 4 * lk + v] + lam_c);
+            }
+            if (step == 3) {   // z[j][i] = P[i][j]
+                *reinterpret_cast<float4*>(z + (16 * cb + lr) * NN + 16 * ra + 4 * lk) =
+                    make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) out[ra][v] = (__bf16)acc[v];
+            }
+        }
+        if (step < 3) {
+            __syncthreads();   // every wave has finished reading X
+#pragma unroll
+            for (int ra = 0; ra < NB; ++ra) *reinterpret_cast<bf4*>(X + (16 * cb + lr) * LD + 16 * ra + 4 * lk) = out[ra];
+            __syncthreads();
+        }
+    }
+    __syncthreads();   // z complete for every thread of the workgroup
+}
+
+__global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
+                                                            const __bf16* __restrict__ Stab,
+                                                            const float* __restrict__ lamtab) {
+    __shared__ __align__(16) __bf16 X[256 * D256_LD];
+    const int64_t base = (int64_t)blockIdx.x * 256 * 256;
+    dst256_apply(rin + base, zout + base, X, Stab, lamtab);
+}
+
+// DST: fast-Poisson-preconditioned CG (grid 256 only, T = float, X = D256_BYTES of LDS);
+// otherwise Jacobi-scaled CG on any grid.
+template <typename T, bool ADJ, bool DST = false>
 __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t row, const int NN,
-                                               const int32_t* __restrict__ obs, SolveShared& sh) {
+                                               const int32_t* __restrict__ obs, SolveShared& sh,
+                                               __bf16* X = nullptr, const __bf16* __restrict__ Stab = nullptr,
+                                               const float* __restrict__ lamtab = nullptr) {
     constexpr int NW = 16;
+    static_assert(!DST || sizeof(T) == 4, "the preconditioned global solver runs in FP32");
     double* red1 = sh.red1;
     double* red2 = sh.red2;
     double* src_w = sh.src_w;
@@ -499,8 +578,16 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
     T* pv = vb + 3 * nodes;
     T* qv = vb + 4 * nodes;
     T* yv = vb + 5 * nodes;
+    T* zv = vb + 6 * nodes;   // preconditioned residual (DST)
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     auto interior = [&](int g, int c) { return c < NN - 1 && g < NN - 1; };
+    int napp = 0;
+    auto precondition = [&]() {   // zv = L^{-1} rv
+        if constexpr (DST) {
+            dst256_apply(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), X, Stab, lamtab);
+            ++napp;
+        }
+    };
 
     for (int k = tid; k < nodes; k += 1024) {
         const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
@@ -592,6 +679,16 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             double tacc = 0.0;
             for (int k = tid; k < nodes; k += 1024) tacc += (double)rv[k] * (double)rv[k];
             double rr = block_sum<NW>(tacc, red1);
+            double rz = rr;
+            if constexpr (DST) {   // p = z = L^{-1} r
+                precondition();
+                double zacc = 0.0;
+                for (int k = tid; k < nodes; k += 1024) {
+                    zacc += (double)rv[k] * (double)zv[k];
+                    pv[k] = zv[k];
+                }
+                rz = block_sum<NW>(zacc, red2);
+            }
             const double target = a.tol_inner * a.tol_inner * rr;
             bool broke = false;
             while (rr > target) {
@@ -615,7 +712,7 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                 }
                 const double pq = block_sum<NW>((double)pq_acc, red1);
                 if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
-                const T alpha = (T)(rr / pq);
+                const T alpha = (T)(rz / pq);
                 T r_acc = T(0);
                 for (int k = tid; k < nodes; k += 1024) {
                     xv[k] += alpha * pv[k];
@@ -624,10 +721,23 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                     r_acc += rk * rk;
                 }
                 const double rrn = block_sum<NW>((double)r_acc, red2);
-                const T beta = (T)(rrn / rr);
-                rr = rrn;
-                for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
                 ++total;
+                if constexpr (DST) {
+                    rr = rrn;
+                    if (!(rr > target)) break;
+                    precondition();
+                    double zacc = 0.0;
+                    for (int k = tid; k < nodes; k += 1024) zacc += (double)rv[k] * (double)zv[k];
+                    const double rzn = block_sum<NW>(zacc, red1);
+                    const T beta = (T)(rzn / rz);
+                    rz = rzn;
+                    for (int k = tid; k < nodes; k += 1024) pv[k] = zv[k] + beta * pv[k];
+                } else {
+                    const T beta = (T)(rrn / rr);
+                    rr = rrn;
+                    rz = rr;
+                    for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
+                }
             }
             for (int k = tid; k < nodes; k += 1024) {
                 const double corr = sd[k] * (double)xv[k];
@@ -647,6 +757,7 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             atomicAdd(&a.stats[0], (unsigned long long)total);
             atomicAdd(&a.stats[1], (unsigned long long)sweeps);
             atomicAdd(&a.stats[2], (unsigned long long)solves);
+            if (DST) atomicAdd(&a.stats[3], (unsigned long long)napp);
         }
     }
     __syncthreads();
@@ -656,6 +767,14 @@ template <typename T, bool ADJ>
 __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
     __shared__ SolveShared sh;
     cg_global_body<T, ADJ>(a, blockIdx.x, NN, a.obs, sh);
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(1024) void cg_global_dst256(SolveArgs a, const __bf16* __restrict__ Stab,
+                                                         const float* __restrict__ lamtab) {
+    __shared__ __align__(16) __bf16 X[256 * D256_LD];
+    __shared__ SolveShared sh;
+    cg_global_body<float, ADJ, true>(a, blockIdx.x, 256, a.obs, sh, X, Stab, lamtab);
 }
 
 // 1D: the tridiagonal flux-form system has the closed-form solution
@@ -777,6 +896,12 @@ __device__ __noinline__ void mixed_global(const SolveArgs& a, int64_t p, int n, 
     cg_global_body<T, false>(a, p, n, obs, g_mixed_sh);
 }
 
+static_assert(D256_BYTES <= MIXED_SMEM, "mixed-grid LDS");
+__device__ __noinline__ void mixed_global_dst256(const SolveArgs& a, int64_t p, const int32_t* obs, const __bf16* S,
+                                                 const float* lam) {
+    cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<__bf16*>(g_mixed_smem), S, lam);
+}
+
 template <int PREC, bool DST>
 __global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTable lt,
                                                            const int32_t* __restrict__ level,
@@ -800,6 +925,8 @@ __global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTab
                 mixed_onchip<float, 64, 4, DST>(a, p, lt.obs[l], S, lt.lam[l]);
             else if (n == 128)
                 mixed_onchip<float, 128, 16, DST>(a, p, lt.obs[l], S, lt.lam[l]);
+            else if (n == 256 && DST)
+                mixed_global_dst256(a, p, lt.obs[l], S, lt.lam[l]);
             else if (n == 256)
                 mixed_global<float>(a, p, 256, lt.obs[l]);
         } else {
@@ -865,7 +992,7 @@ static hipError_t run_global(int64_t N, const SolveArgs& a, int n, hipStream_t s
     return hipGetLastError();
 }
 
-bool dst_supported(int n) { return n == 32 || n == 64 || n == 128; }
+bool dst_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 
 hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
     if (N <= 0) return hipSuccess;
@@ -873,6 +1000,14 @@ hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* 
         case 32: return run_onchip<float, 32, 4, true>(N, a, S, lam, s);
         case 64: return run_onchip<float, 64, 8, true>(N, a, S, lam, s);
         case 128: return run_onchip<float, 128, 16, true>(N, a, S, lam, s);
+        case 256: {
+            const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+            if (a.lam)
+                cg_global_dst256<true><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, Sb, lam);
+            else
+                cg_global_dst256<false><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, Sb, lam);
+            return hipGetLastError();
+        }
         default: return hipErrorInvalidValue;
     }
 }

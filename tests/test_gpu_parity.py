@@ -126,13 +126,13 @@ def test_forward_fp32_refine(name, grid, N):
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
     assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
-    if grid in (32, 64, 128):                           # fast-Poisson preconditioner: grid-independent
+    if grid in (32, 64, 128, 256):                      # fast-Poisson preconditioner: grid-independent
         assert (it.cpu().numpy() < 60).all(), it
     ref_phi = potential(ref, op.y, op.sigma)
     assert np.abs(phi.cpu().numpy() / ref_phi - 1).max() <= 1e-4
 
 
-@pytest.mark.parametrize("grid", [32, 64, 128])
+@pytest.mark.parametrize("grid", [32, 64, 128, 256])
 def test_fast_poisson_preconditioner(grid):
     """z = L^{-1} r up to a constant, against the same formula in FP64 (bf16 transforms: 2e-2)."""
     from paper_2503_16028_amd import smc
@@ -156,7 +156,7 @@ def test_fast_poisson_preconditioner(grid):
         assert np.abs(got[k, n - 1, :]).max() == 0 and np.abs(got[k, :, n - 1]).max() == 0
 
 
-@pytest.mark.parametrize("name,grid,N", [("t2", 32, 9), ("c2", 64, 5), ("c3", 128, 4)])
+@pytest.mark.parametrize("name,grid,N", [("t2", 32, 9), ("c2", 64, 5), ("c3", 128, 4), ("c5", 256, 1)])
 def test_forward_fp32_jacobi_only(name, grid, N):
     """The Jacobi-preconditioned FP32 path (the fast-Poisson one is the default on these grids)."""
     from paper_2503_16028_amd import smc
