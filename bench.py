@@ -160,6 +160,7 @@ def main():
     torch.cuda.set_device(dev)
     p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-5)
     unknowns = (GRID - 1) ** 2
+    tile, tile_ms = smc.smc_autotune(p, 0, N, reps=2)      # tile shape of the solver, before timing
 
     def stage_loop(prec, steps, warmup, n_moves):
         s = SMCSampler(p, N, M, n_moves, ess_frac=0.5, beta0=0.2, prec=prec, seed=2503, device=dev)
@@ -264,11 +265,12 @@ def main():
                              "inside FP64 residual refinement to 1e-10"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK, "traffic": None,
-                     "kernel": "cg_onchip<float,128,16,fast-Poisson>", "kernel_ms_per_launch": kernel_ms,
+                     "kernel": "cg_onchip<float,128,%d,fast-Poisson>" % tile, "kernel_ms_per_launch": kernel_ms,
                      "valu_tflops": valu_flops / (prof32["ms"] * 1e-3) / 1e12,
                      "cg_iters_per_solve": prof32["iters"] / max(1, prof32["solves"]),
                      "precond_apps_per_solve": prof32["precond_apps"] / max(1, prof32["solves"]),
                      "sweeps_per_solve": prof32["sweeps"] / max(1, prof32["solves"])},
+        "autotune": {"rows_per_thread": tile, "ms_per_forward_launch": {str(k): v for k, v in tile_ms.items()}},
         "cpu_baseline": cpu,
         "variants": variants,
     }

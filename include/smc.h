@@ -251,6 +251,24 @@ int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
  * padding and must hold 0 in r.  Grids of 32, 64, 128 and 256 intervals. */
 int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z, smc_stream stream);
 
+/* Tile shape of the fast-Poisson solver of a grid (FP32+refinement, single-grid calls): grid rows
+ * per thread, so that one particle's workgroup has n*n/rows threads.  Different shapes give the
+ * same solution up to rounding (the reduction order changes).
+ *   smc_tile_candidates  the shapes the library has for grid n (rows[8] out, *count out);
+ *                        the first is the default; grid 256 has the single entry 0
+ *   smc_set_tile         choose one for grid `level` (0 = default); smc_get_tile reads it back
+ *   smc_autotune         time every candidate on N synthetic prior particles (drawn by the
+ *                        library into its own workspace), reps timed launches each after one
+ *                        warm-up, keep the fastest; *rows out, ms[count] out (may be NULL): mean
+ *                        milliseconds per forward launch (synthesis and solve) of each candidate.
+ *                        Synchronises `stream`; overwrites the problem's workspace, so no other
+ *                        call on p may be in flight. */
+int smc_tile_candidates(int32_t n, int32_t* rows, int32_t* count);
+int smc_set_tile(smc_problem p, int32_t level, int32_t rows);
+int smc_get_tile(smc_problem p, int32_t level, int32_t* rows);
+int smc_autotune(smc_problem p, int32_t level, int64_t N, int32_t reps, smc_stream stream, int32_t* rows,
+                 double* ms);
+
 /* Solver timing.  smc_profile(p, 1) clears and starts: every forward-solve launch made by
  * smc_forward_batch, smc_forward_state, smc_value_and_grad, smc_gmpcn_move and smc_pcnl_move on p
  * is then bracketed by two HIP events recorded on

@@ -446,7 +446,7 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     if (P.dim == 1)
         e = launch_solve1d(L.n, N, a, s);
     else if (prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S)
-        e = launch_solve2d_dst(L.n, N, a, L.dst_S, L.dst_lam, s);
+        e = launch_solve2d_dst(L.n, L.rows, N, a, L.dst_S, L.dst_lam, s);
     else
         e = launch_solve2d(L.n, prec, N, a, s);
     if (e != hipSuccess) return e;
@@ -691,6 +691,101 @@ extern "C" int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, 
         HIPCHK(launch_pcnl_accept(N, P.K, beta, tau, seed, c, P.ws_v, P.ws_gnew, P.ws_phinew, P.ws_iters, xi, grad,
                                   phi, n_acc, s));
     }
+    return SMC_OK;
+}
+
+// ------------------------------------------------------------------ tile choice and autotuning
+extern "C" int smc_tile_candidates(int32_t n, int32_t* rows, int32_t* count) {
+    if (!rows || !count) return fail(SMC_E_INVAL, "rows and count must not be NULL");
+    int r[8];
+    const int c = tile_candidates(n, r);
+    if (c == 0) return fail(SMC_E_INVAL, "grid %d has no fast-Poisson solver", n);
+    std::copy(r, r + c, rows);
+    *count = c;
+    return SMC_OK;
+}
+
+static int check_tile(const Problem& P, int32_t level, int32_t rows) {
+    if (level < 0 || level >= P.n_levels) return fail(SMC_E_INVAL, "level %d out of range", level);
+    if (P.dim != 2 || !P.lv[level].dst_S) return fail(SMC_E_INVAL, "grid %d has no fast-Poisson solver", P.lv[level].n);
+    if (rows == 0) return SMC_OK;
+    int r[8];
+    const int c = tile_candidates(P.lv[level].n, r);
+    for (int k = 0; k < c; ++k)
+        if (r[k] == rows) return SMC_OK;
+    return fail(SMC_E_INVAL, "grid %d has no tile of %d rows per thread", P.lv[level].n, rows);
+}
+
+extern "C" int smc_set_tile(smc_problem p, int32_t level, int32_t rows) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (int r = check_tile(p->P, level, rows)) return r;
+    p->P.lv[level].rows = rows;
+    return SMC_OK;
+}
+
+extern "C" int smc_get_tile(smc_problem p, int32_t level, int32_t* rows) {
+    if (!p || !rows) return fail(SMC_E_INVAL, "problem and rows must not be NULL");
+    if (int r = check_tile(p->P, level, 0)) return r;
+    int c[8];
+    tile_candidates(p->P.lv[level].n, c);
+    *rows = p->P.lv[level].rows ? p->P.lv[level].rows : c[0];
+    return SMC_OK;
+}
+
+extern "C" int smc_autotune(smc_problem p, int32_t level, int64_t N, int32_t reps, smc_stream stream, int32_t* rows,
+                            double* ms) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    Problem& P = p->P;
+    if (int r = check_tile(P, level, 0)) return r;
+    if (N < 1 || N > P.n_max) return fail(SMC_E_INVAL, "N must be 1..n_max");
+    if (reps < 1 || reps > 100) return fail(SMC_E_INVAL, "reps must be 1..100");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    hipStream_t s = (hipStream_t)stream;
+    int cand[8];
+    const int nc = tile_candidates(P.lv[level].n, cand);
+    const int saved = P.lv[level].rows;
+    const bool prof = P.profiling;
+    P.profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        P.profiling = prof;
+    };
+    auto run = [&](hipError_t e) -> bool {
+        if (e == hipSuccess) return true;
+        P.lv[level].rows = saved;
+        cleanup();
+        fail(SMC_E_HIP, "autotune: %s", hipGetErrorString(e));
+        return false;
+    };
+    if (!run(hipEventCreate(&e0)) || !run(hipEventCreate(&e1))) return SMC_E_HIP;
+    // synthetic particles: prior draws of the library's own generator, in the proposal workspace
+    if (!run(launch_prior(N, P.K, 0x5EED, 0, P.ws_v, s))) return SMC_E_HIP;
+    int best = cand[0];
+    double best_ms = INFINITY;
+    for (int k = 0; k < nc; ++k) {
+        P.lv[level].rows = cand[k];
+        Solve o;
+        o.phi = P.ws_phinew;
+        o.iters = P.ws_iters;
+        if (!run(forward(p, level, SMC_FP32_REFINE, N, P.ws_v, o, s))) return SMC_E_HIP;   // warm-up
+        if (!run(hipEventRecord(e0, s))) return SMC_E_HIP;
+        for (int r = 0; r < reps; ++r)
+            if (!run(forward(p, level, SMC_FP32_REFINE, N, P.ws_v, o, s))) return SMC_E_HIP;
+        if (!run(hipEventRecord(e1, s)) || !run(hipEventSynchronize(e1))) return SMC_E_HIP;
+        float t = 0.0f;
+        if (!run(hipEventElapsedTime(&t, e0, e1))) return SMC_E_HIP;
+        const double per = (double)t / reps;
+        if (ms) ms[k] = per;
+        if (per < best_ms) {
+            best_ms = per;
+            best = cand[k];
+        }
+    }
+    P.lv[level].rows = best;
+    if (rows) *rows = best;
+    cleanup();
     return SMC_OK;
 }
 

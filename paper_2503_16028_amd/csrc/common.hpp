@@ -20,6 +20,7 @@ struct Level {
     int32_t* obs_node = nullptr; // [n_obs] flat nodal index (2D j*(n+1)+i, 1D i)
     void* dst_S = nullptr;       // [n][n] bf16 sine transform (fast-Poisson preconditioner)
     float* dst_lam = nullptr;    // [n] its 1D eigenvalues sin^2(pi (k+1) / 2n)
+    int rows = 0;                // tile of the fast-Poisson solver: grid rows per thread (0 = default)
 };
 
 struct Problem {
@@ -218,7 +219,9 @@ hipError_t launch_pcnl_accept(int64_t N, int K, double beta, double tau, uint64_
 hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStream_t s);
 hipError_t launch_solve1d(int n, int64_t N, const SolveArgs& a, hipStream_t s);
 bool dst_supported(int n);
-hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s);
+int tile_candidates(int n, int* rows);
+hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, const void* S, const float* lam,
+                              hipStream_t s);
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
                             hipStream_t s);
 

@@ -994,13 +994,34 @@ static hipError_t run_global(int64_t N, const SolveArgs& a, int n, hipStream_t s
 
 bool dst_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 
-hipError_t launch_solve2d_dst(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
-    if (N <= 0) return hipSuccess;
+// Tile shapes of the fast-Poisson solver: rows of the grid per thread (the workgroup has n * n / rows
+// threads); the first is the default.  The 256 grid runs the global-memory solver (no choice).
+int tile_candidates(int n, int* rows) {
     switch (n) {
-        case 32: return run_onchip<float, 32, 4, true>(N, a, S, lam, s);
-        case 64: return run_onchip<float, 64, 8, true>(N, a, S, lam, s);
-        case 128: return run_onchip<float, 128, 16, true>(N, a, S, lam, s);
-        case 256: {
+        case 32: rows[0] = 4; rows[1] = 8; return 2;
+        case 64: rows[0] = 8; rows[1] = 4; rows[2] = 16; return 3;
+        case 128: rows[0] = 16; rows[1] = 32; return 2;
+        case 256: rows[0] = 0; return 1;
+        default: return 0;
+    }
+}
+
+hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, const void* S, const float* lam,
+                              hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const int key = n * 64 + rows;
+    switch (key) {
+        case 32 * 64 + 0:
+        case 32 * 64 + 4: return run_onchip<float, 32, 4, true>(N, a, S, lam, s);
+        case 32 * 64 + 8: return run_onchip<float, 32, 8, true>(N, a, S, lam, s);
+        case 64 * 64 + 0:
+        case 64 * 64 + 8: return run_onchip<float, 64, 8, true>(N, a, S, lam, s);
+        case 64 * 64 + 4: return run_onchip<float, 64, 4, true>(N, a, S, lam, s);
+        case 64 * 64 + 16: return run_onchip<float, 64, 16, true>(N, a, S, lam, s);
+        case 128 * 64 + 0:
+        case 128 * 64 + 16: return run_onchip<float, 128, 16, true>(N, a, S, lam, s);
+        case 128 * 64 + 32: return run_onchip<float, 128, 32, true>(N, a, S, lam, s);
+        case 256 * 64 + 0: {
             const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
             if (a.lam)
                 cg_global_dst256<true><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, Sb, lam);

@@ -66,6 +66,10 @@ _SIGS = {
                                        c_vp, ctypes.POINTER(c_vp)]),
     "smc_stage_graph_launch": (c_i32, [c_vp, c_vp]),
     "smc_stage_graph_destroy": (None, [c_vp]),
+    "smc_tile_candidates": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "smc_set_tile": (c_i32, [c_vp, c_i32, c_i32]),
+    "smc_get_tile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
+    "smc_autotune": (c_i32, [c_vp, c_i32, c_i64, c_i32, c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl)]),
     "smc_temper": (c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_resample": (c_i32, [c_i64, c_vp, c_u64, c_vp, c_vp, c_vp]),
     "smc_gather": (c_i32, [c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -300,6 +304,32 @@ class StageGraph:
             self.close()
         except Exception:
             pass
+
+
+def smc_tile_candidates(n):
+    rows = (c_i32 * 8)()
+    count = c_i32()
+    _check(lib().smc_tile_candidates(int(n), rows, ctypes.byref(count)))
+    return [rows[k] for k in range(count.value)]
+
+
+def smc_set_tile(problem, level, rows):
+    _check(lib().smc_set_tile(problem.handle, int(level), int(rows)))
+
+
+def smc_get_tile(problem, level):
+    out = c_i32()
+    _check(lib().smc_get_tile(problem.handle, int(level), ctypes.byref(out)))
+    return out.value
+
+
+def smc_autotune(problem, level, N, reps=2, stream=None):
+    """Time every tile candidate of grid `level`; keep the fastest.  Returns (rows, {rows: ms})."""
+    cands = smc_tile_candidates(problem.grids[level])
+    ms = (c_dbl * 8)()
+    out = c_i32()
+    _check(lib().smc_autotune(problem.handle, int(level), int(N), int(reps), _stream(stream), ctypes.byref(out), ms))
+    return out.value, {c: ms[k] for k, c in enumerate(cands)}
 
 
 def smc_temper(N, phi, tau_in, ess_frac, h, tau_new, W, log_z_inc, flags=None, stream=None):

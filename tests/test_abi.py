@@ -86,3 +86,21 @@ def test_checkpoint_policy():
     assert choose_checkpoint("recompute", 1, 16, 1 << 40) == "recompute"
     with pytest.raises(ValueError):
         choose_checkpoint("keep", 1, 16, 0)
+
+
+def test_tile_candidates():
+    """Every fast-Poisson tile shape fits one workgroup and the transform's wave tiling
+    (16 x 16 output tiles shared evenly by the waves, whole strips of S per wave)."""
+    from paper_2503_16028_amd import smc
+    for n in (32, 64, 128):
+        cands = smc.smc_tile_candidates(n)
+        assert len(cands) >= 2 and len(set(cands)) == len(cands)
+        for rows in cands:
+            threads = n * n // rows
+            waves = threads // 64
+            nb = n // 16
+            assert n % rows == 0 and threads % 64 == 0 and threads <= 1024
+            assert (nb * nb) % waves == 0 and waves % nb == 0
+    assert smc.smc_tile_candidates(256) == [0]
+    with pytest.raises(smc.SMCError):
+        smc.smc_tile_candidates(16)
