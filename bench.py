@@ -25,6 +25,27 @@ FP32_VECTOR_PEAK = 157.3e12     # MI355X published FP32 vector peak
 BF16_MFMA_PEAK = 2.5e15         # MI355X published dense bf16 matrix peak
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "cg_onchip_128x32_fastpoisson_c3_counters.md")
+SOLVER_SOURCES = [os.path.join(ROOT, "paper_2503_16028_amd", "csrc", f) for f in ("k_solve.hip", "common.hpp")]
+
+
+def measured_traffic(tile):
+    """HBM bytes per solve launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
+    each calibrated against a copy of known size), or None once the solver sources or the tile
+    shape differ from what was profiled."""
+    import hashlib
+    try:
+        fields = dict(l.strip().split(" = ", 1) for l in open(COUNTERS) if " = " in l and l.startswith("    "))
+        h = hashlib.sha256()
+        for f in SOLVER_SOURCES:
+            h.update(open(f, "rb").read())
+        if h.hexdigest() != fields.get("source_sha256") or int(fields.get("tile_rows", -1)) != tile:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(d, sample_per_worker=40):
     """The oracle, as it stands, on a bounded sample of the workload: `workers` processes each
     run one pCN-GM move for `sample_per_worker` particles (one sparse direct solve each)."""
@@ -264,7 +285,8 @@ def main():
                    "solver": "Jacobi-scaled CG in FP32, fast-Poisson (bf16 MFMA sine transform) preconditioner, "
                              "inside FP64 residual refinement to 1e-10"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK, "traffic": measured_traffic(tile),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "cg_onchip<float,128,%d,fast-Poisson>" % tile, "kernel_ms_per_launch": kernel_ms,
                      "valu_tflops": valu_flops / (prof32["ms"] * 1e-3) / 1e12,
                      "cg_iters_per_solve": prof32["iters"] / max(1, prof32["solves"]),
