@@ -186,6 +186,153 @@ struct SolveShared {
     int src_at[MAX_OBS];
 };
 
+// The FP64 passes over one thread's strip (column c, rows g0 .. g0 + R - 1).  They run outside the
+// conjugate-gradient loop and are bound by the latency of their global loads, so each is a separate
+// function: register-allocated on its own, it can unroll the strip and keep many loads in flight
+// without taking registers from the loop.  Pointers are cast back to their address spaces (the
+// call passes them as generic pointers).
+typedef const __attribute__((address_space(1))) double* gcdp;
+typedef __attribute__((address_space(1))) double* gdp;
+
+// Right-hand side of the pass at interior unknown `flat`: f, or the adjoint's point sources.
+__device__ __forceinline__ double strip_rhs(int flat, bool sources, double f, const double* src_w, const int* src_at,
+                                            int n_obs) {
+    if (!sources) return f;
+    double s = 0.0;
+    for (int k = 0; k < n_obs; ++k) s += (src_at[k] == flat) ? src_w[k] : 0.0;
+    return s;
+}
+
+// Scaled residual D^{-1/2} (f - A x) of the strip into its LDS slots (x = 0 when `zero_x`);
+// returns the sum of squares of the unscaled residual.  Every load has a clamped, in-bounds index
+// and a select discards what lies outside the domain, so the strip is straight-line code whose
+// loads the compiler can issue rows ahead.
+template <typename T, int NN, int R, bool SRC>
+__device__ __noinline__ double strip_residual(const double* e_, const double* xo_, const double* sd_, T* tb_, int c,
+                                              int g0, bool zero_x, double f, const double* src_w,
+                                              const int* src_at, int n_obs) {
+    constexpr int NP1 = NN + 1;
+    const double inv_h2 = (double)NN * (double)NN;
+    gcdp e = (gcdp)e_;
+    gcdp xo = (gcdp)xo_;
+    gcdp sd = (gcdp)sd_;
+    __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
+    const int i = c + 1;
+    const bool colin = c < NN - 1;
+    const int cE = min(c + 1, NN - 1), cW = max(c - 1, 0), iE = min(i + 1, NN);
+    double acc = 0.0;
+    if (zero_x) {
+#pragma unroll 8
+        for (int r = 0; r < R; ++r) {
+            const int g = g0 + r;
+            const bool in = colin && g < NN - 1;
+            const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
+            const double sdv = sd[g * NN + c];
+            acc += in ? fr * fr : 0.0;
+            tb[NN + 1 + r * NN] = in ? (T)(sdv * fr) : T(0);
+        }
+        return acc;
+    }
+    double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
+    double xS = xo[max(g0 - 1, 0) * NN + c], xC = xo[g0 * NN + c];
+    xS = (g0 > 0 && colin) ? xS : 0.0;
+    xC = (g0 < NN - 1 && colin) ? xC : 0.0;
+    constexpr int B = R < 8 ? R : 8;   // rows whose loads are issued together
+    static_assert(R % B == 0, "strip blocking");
+#pragma unroll 1
+    for (int r0 = 0; r0 < R; r0 += B) {
+        double eN[B], eE[B], eW[B], xN[B], xE[B], xW[B], sdv[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int g = g0 + r0 + k, j = g + 1;
+            eN[k] = e[min(j + 1, NN) * NP1 + i];
+            eE[k] = e[j * NP1 + iE];
+            eW[k] = e[j * NP1 + i - 1];
+            xN[k] = xo[min(g + 1, NN - 1) * NN + c];
+            xE[k] = xo[g * NN + cE];
+            xW[k] = xo[g * NN + cW];
+            sdv[k] = sd[g * NN + c];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int r = r0 + k, g = g0 + r, j = g + 1;
+            const double xn = (g + 1 < NN - 1 && colin) ? xN[k] : 0.0;
+            const double xe = (c + 1 < NN - 1) ? xE[k] : 0.0;
+            const double xw = (c > 0) ? xW[k] : 0.0;
+            const bool in = colin && g < NN - 1;
+            const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
+            const double res =
+                fr - eC * inv_h2 * (eE[k] * (xC - xe) + eW[k] * (xC - xw) + eN[k] * (xC - xn) + eS * (xC - xS));
+            acc += in ? res * res : 0.0;
+            tb[NN + 1 + r * NN] = in ? (T)(sdv[k] * res) : T(0);
+            eS = eC;
+            eC = (j + 1 <= NN) ? eN[k] : 0.0;
+            xS = xC;
+            xC = xn;
+        }
+    }
+    return acc;
+}
+
+// x += D^{-1/2} y for the strip, y staged in its LDS slots (x = D^{-1/2} y when `first`).
+template <typename T, int NN, int R>
+__device__ __noinline__ void strip_update(double* xo_, const double* sd_, const T* tb_, int c, int g0, bool first) {
+    gdp xo = (gdp)xo_;
+    gcdp sd = (gcdp)sd_;
+    const __attribute__((address_space(3))) T* tb = (const __attribute__((address_space(3))) T*)tb_;
+    constexpr int B = R < 8 ? R : 8;
+#pragma unroll 1
+    for (int r0 = 0; r0 < R; r0 += B) {
+        double sdv[B], xv[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int g = g0 + r0 + k;
+            sdv[k] = sd[g * NN + c];
+            xv[k] = first ? 0.0 : xo[g * NN + c];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int g = g0 + r0 + k;
+            xo[g * NN + c] = xv[k] + sdv[k] * (double)tb[NN + 1 + (r0 + k) * NN];
+        }
+    }
+}
+
+// D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots.
+template <typename T, int NN, int R>
+__device__ __noinline__ void strip_setup(const double* e_, double* sd_, T* tb_, int c, int g0) {
+    constexpr int NP1 = NN + 1;
+    const double h = 1.0 / NN;
+    gcdp e = (gcdp)e_;
+    gdp sd = (gdp)sd_;
+    __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
+    const int i = c + 1;
+    const int iE = min(i + 1, NN);
+    double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
+    constexpr int B = R < 8 ? R : 8;
+#pragma unroll 1
+    for (int r0 = 0; r0 < R; r0 += B) {
+        double eN[B], eE[B], eW[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int j = g0 + r0 + k + 1;
+            eN[k] = e[min(j + 1, NN) * NP1 + i];
+            eE[k] = e[j * NP1 + iE];
+            eW[k] = e[j * NP1 + i - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int r = r0 + k, g = g0 + r, j = g + 1;
+            const bool in = c < NN - 1 && g < NN - 1;
+            const double S = eE[k] + eW[k] + eN[k] + eS;
+            sd[g * NN + c] = in ? h / sqrt(eC * S) : 1.0;
+            tb[NN + 1 + r * NN] = in ? (T)sqrt(eC / S) : T(0);
+            eS = eC;
+            eC = (j + 1 <= NN) ? eN[k] : 0.0;
+        }
+    }
+}
+
 // One particle's solve by the whole workgroup (NN * NN / R threads); `smem` holds at least
 // onchip_smem<T, NN, R, DST>() bytes.  Used by the per-grid kernel and by the mixed-grid one.
 template <typename T, int NN, int R, bool DST, bool ADJ>
@@ -199,6 +346,8 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     using DS = DstShape<NN, NW>;
     static_assert(!DST || (NN >= 32 && (DS::NB * DS::NB) % NW == 0 && NW % DS::NB == 0), "transform tiling");
     static_assert(NW <= 16, "reduction slots");
+    // FP64 passes as separate, unrolled functions (wide strips); inline loops otherwise
+    constexpr bool SPLIT = R >= 32;
     double* red1 = sh.red1;
     double* red2 = sh.red2;
     double* src_w = sh.src_w;
@@ -219,9 +368,10 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
         ly[k] = T(0);
         ly[PAD + NN * NN + k] = T(0);
     }
-    // ---- setup: D^{-1/2} (FP64, workspace) and t (registers); work outside the CG loop runs
-    // as plain loops that stage through the thread's own LDS slots
-    {
+    // ---- setup: D^{-1/2} (FP64, workspace) and t (registers), staged through the thread's own LDS slots
+    if constexpr (SPLIT) {
+        strip_setup<T, NN, R>(e, sd, tb, c, b * R);
+    } else {
         // column i of e, rows j-1, j, j+1 carried along the strip (j = g + 1)
         double eS = e[(b * R) * NP1 + i], eC = e[(b * R + 1) * NP1 + i];
 #pragma unroll 1
@@ -306,6 +456,12 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
         for (int sweep = 0;; ++sweep) {
             ++sweeps;
             double acc = 0.0;
+            if constexpr (SPLIT) {
+                acc = (pass == 1) ? strip_residual<T, NN, R, true>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
+                                                                   src_at, a.n_obs)
+                                  : strip_residual<T, NN, R, false>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
+                                                                    src_at, a.n_obs);
+            } else
             if (sweep == 0) {
 #pragma unroll 1
                 for (int r = 0; r < R; ++r) {
@@ -445,11 +601,15 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = x[r];
+            if constexpr (SPLIT) {
+                strip_update<T, NN, R>(xo, sd, tb, c, b * R, sweep == 0);
+            } else {
 #pragma unroll 1
-            for (int r = 0; r < R; ++r) {
-                const int g = b * R + r;
-                const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
-                xo[g * NN + c] = (sweep == 0) ? corr : xo[g * NN + c] + corr;
+                for (int r = 0; r < R; ++r) {
+                    const int g = b * R + r;
+                    const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
+                    xo[g * NN + c] = (sweep == 0) ? corr : xo[g * NN + c] + corr;
+                }
             }
             __syncthreads();
             if (broke) break;
@@ -1000,7 +1160,7 @@ int tile_candidates(int n, int* rows) {
     switch (n) {
         case 32: rows[0] = 4; rows[1] = 8; return 2;
         case 64: rows[0] = 8; rows[1] = 4; rows[2] = 16; return 3;
-        case 128: rows[0] = 16; rows[1] = 32; return 2;
+        case 128: rows[0] = 32; rows[1] = 16; return 2;
         case 256: rows[0] = 0; return 1;
         default: return 0;
     }
@@ -1018,8 +1178,8 @@ hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, co
         case 64 * 64 + 8: return run_onchip<float, 64, 8, true>(N, a, S, lam, s);
         case 64 * 64 + 4: return run_onchip<float, 64, 4, true>(N, a, S, lam, s);
         case 64 * 64 + 16: return run_onchip<float, 64, 16, true>(N, a, S, lam, s);
-        case 128 * 64 + 0:
         case 128 * 64 + 16: return run_onchip<float, 128, 16, true>(N, a, S, lam, s);
+        case 128 * 64 + 0:
         case 128 * 64 + 32: return run_onchip<float, 128, 32, true>(N, a, S, lam, s);
         case 256 * 64 + 0: {
             const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
