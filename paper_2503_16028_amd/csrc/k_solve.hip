@@ -32,6 +32,7 @@
 namespace smc {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f32_16x16x32_bf16 lane layout, checked on the device:
@@ -46,27 +47,37 @@ template <int NN, int NW>
 struct DstShape {
     static constexpr int NB = NN / 16;        // 16 x 16 tiles per dimension
     static constexpr int KS = NN / 32;        // k steps of 32
-    static constexpr int TPW = NB * NB / NW;  // output tiles per wave
+    // strips of S per wave: two when there are no more waves than strips, so that every operand
+    // fragment read from LDS feeds two matrix products
+    static constexpr int SP = (NW <= NB && NB % 2 == 0) ? 2 : 1;
+    static constexpr int NSG = NB / SP;       // strip groups
+    static constexpr int TPW = NB * NB / (NW * SP);   // output tiles per wave and strip
     static constexpr int LD = NN + 8;         // bf16 row stride (16-byte aligned, spreads banks)
     static constexpr int LDZ = NN + 4;        // fp32 row stride of the result
     static constexpr int BYTES = 2 * NN * LD * 2 + NN * LDZ * 4;
+    static_assert(NW % NSG == 0 && (NB * NB) % (NW * SP) == 0, "transform tiling");
 };
 
 template <typename T, int NN, int R, int NW>
 __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem, const __bf16* __restrict__ Stab,
                                           const float* __restrict__ lamtab, int c, int b, int wave, int lane) {
     using DS = DstShape<NN, NW>;
-    constexpr int LD = DS::LD, LDZ = DS::LDZ, KS = DS::KS, TPW = DS::TPW, NB = DS::NB;
+    constexpr int LD = DS::LD, LDZ = DS::LDZ, KS = DS::KS, TPW = DS::TPW, SP = DS::SP, NSG = DS::NSG;
     __bf16* bufA = reinterpret_cast<__bf16*>(smem);   // R^T, later T2^T
     __bf16* bufB = bufA + NN * LD;                    // T1, later T3
     float* Z = reinterpret_cast<float*>(bufB + NN * LD);   // Z[g][c]: lanes of a row read consecutive words
     const int lr = lane & 15, lk = lane >> 4;
-    const int sb = wave % NB, wq = wave / NB;
-    bf8 sfrag[KS];   // rows sb*16.. of S (symmetric: also columns sb*16.. as a B operand)
+    const int sg = wave % NSG, wq = wave / NSG;
+    bf8 sfrag[SP][KS];   // rows (sg SP + s) 16.. of S (symmetric: also columns, as a B operand)
+    float lam_col[SP];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-        sfrag[ks] = *reinterpret_cast<const bf8*>(Stab + (sb * 16 + lr) * NN + 32 * ks + 8 * lk);
-    const float lam_col = lamtab[sb * 16 + lr];
+    for (int q = 0; q < SP; ++q) {
+        const int sb = sg * SP + q;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            sfrag[q][ks] = *reinterpret_cast<const bf8*>(Stab + (sb * 16 + lr) * NN + 32 * ks + 8 * lk);
+        lam_col[q] = lamtab[sb * 16 + lr];
+    }
     {   // stage R^T[c][g] = bf16(r): the thread's strip is contiguous
         __bf16* dst = bufA + c * LD + b * R;
         if constexpr (R % 8 == 0) {
@@ -83,51 +94,89 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
         }
     }
     __syncthreads();
+    // Each product is ordered so that the four values a lane holds in its 16 x 16 result tile
+    // are consecutive in the layout the next product reads (one 8-byte or 16-byte store per tile),
+    // while both operands stay contiguous along the contraction index.
 #pragma unroll 1
-    for (int tt = 0; tt < TPW; ++tt) {   // T1[k][c] = sum_g S[k][g] R[g][c]
+    for (int tt = 0; tt < TPW; ++tt) {   // T1[k][c] = sum_g S[k][g] R[g][c], as (R^T S)[c][k]
         const int cb = wq * TPW + tt;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        f4 acc[SP];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = mfma_bf16(sfrag[ks], *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk), acc);
+        for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) bufB[(sb * 16 + 4 * lk + v) * LD + cb * 16 + lr] = (__bf16)acc[v];
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 av = *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SP; ++q) {
+            bf4 o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = (__bf16)acc[q][v];
+            *reinterpret_cast<bf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
+        }
     }
     __syncthreads();
 #pragma unroll 1
     for (int tt = 0; tt < TPW; ++tt) {   // T2^T[l][k] = (sum_c T1[k][c] S[c][l]) / (lam_k + lam_l)
         const int rb = wq * TPW + tt;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        f4 acc[SP];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = mfma_bf16(*reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk), sfrag[ks], acc);
+        for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int k = rb * 16 + 4 * lk + v;
-            bufA[(sb * 16 + lr) * LD + k] = (__bf16)(acc[v] * __builtin_amdgcn_rcpf(lamtab[k] + lam_col));
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 av = *reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SP; ++q) {
+            bf4 o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                o[v] = (__bf16)(acc[q][v] * __builtin_amdgcn_rcpf(lamtab[rb * 16 + 4 * lk + v] + lam_col[q]));
+            *reinterpret_cast<bf4*>(bufA + ((sg * SP + q) * 16 + lr) * LD + rb * 16 + 4 * lk) = o;
         }
     }
     __syncthreads();
 #pragma unroll 1
-    for (int tt = 0; tt < TPW; ++tt) {   // T3[g][l] = sum_k S[g][k] T2[k][l]
+    for (int tt = 0; tt < TPW; ++tt) {   // T3[g][l] = sum_k S[g][k] T2[k][l], as (T2^T S)[l][g]
         const int cb = wq * TPW + tt;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        f4 acc[SP];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = mfma_bf16(sfrag[ks], *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk), acc);
+        for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) bufB[(sb * 16 + 4 * lk + v) * LD + cb * 16 + lr] = (__bf16)acc[v];
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 av = *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SP; ++q) {
+            bf4 o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = (__bf16)acc[q][v];
+            *reinterpret_cast<bf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
+        }
     }
     __syncthreads();
 #pragma unroll 1
-    for (int tt = 0; tt < TPW; ++tt) {   // Z[g][c] = sum_l T3[g][l] S[l][c]
+    for (int tt = 0; tt < TPW; ++tt) {   // Z[g][c] = sum_l T3[g][l] S[l][c], as (S T3^T)[c][g]
         const int rb = wq * TPW + tt;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        f4 acc[SP];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = mfma_bf16(*reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk), sfrag[ks], acc);
+        for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Z[(rb * 16 + 4 * lk + v) * LDZ + sb * 16 + lr] = acc[v];
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf8 bv = *reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(sfrag[q][ks], bv, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < SP; ++q)
+            *reinterpret_cast<float4*>(Z + (rb * 16 + lr) * LDZ + (sg * SP + q) * 16 + 4 * lk) =
+                make_float4(acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
     }
     __syncthreads();
 }
@@ -203,14 +252,41 @@ __device__ __forceinline__ double strip_rhs(int flat, bool sources, double f, co
     return s;
 }
 
+// A pointer every lane holds, made visibly wave-uniform (its loads can then go through the
+// scalar unit; used only for data the kernel does not write).
+__device__ __forceinline__ const double* wave_uniform(const double* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (const double*)(((unsigned long long)hi << 32) | lo);
+}
+
+// The value `v` of the next lane (lane 63: `edge`) and of the previous lane (lane 0: `edge`), by
+// DPP wave shifts: a thread's east and west neighbours are the adjacent lanes of its wave.
+__device__ __forceinline__ double from_next_lane(double v, double edge) {
+    const long long b = __double_as_longlong(v), be = __double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)be, (int)b, 0x130, 0xF, 0xF, false);   // wave_shl:1
+    const int hi = __builtin_amdgcn_update_dpp((int)(be >> 32), (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double from_prev_lane(double v, double edge) {
+    const long long b = __double_as_longlong(v), be = __double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)be, (int)b, 0x138, 0xF, 0xF, false);   // wave_shr:1
+    const int hi = __builtin_amdgcn_update_dpp((int)(be >> 32), (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Scaled residual D^{-1/2} (f - A x) of the strip into its LDS slots (x = 0 when `zero_x`);
 // returns the sum of squares of the unscaled residual.  Every load has a clamped, in-bounds index
 // and a select discards what lies outside the domain, so the strip is straight-line code whose
-// loads the compiler can issue rows ahead.
+// loads are issued 8 rows at a time.  The east and west values of e and x come from the adjacent
+// lanes; only the two wave edges load them (e, read-only here, through the scalar unit).
 template <typename T, int NN, int R, bool SRC>
-__device__ __noinline__ double strip_residual(const double* e_, const double* xo_, const double* sd_, T* tb_, int c,
-                                              int g0, bool zero_x, double f, const double* src_w,
-                                              const int* src_at, int n_obs) {
+__device__ __noinline__ double strip_residual(const double* __restrict__ e_, const double* __restrict__ xo_,
+                                              const double* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
+                                              bool zero_x, double f, const double* __restrict__ src_w,
+                                              const int* __restrict__ src_at, int n_obs) {
+    static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
     constexpr int NP1 = NN + 1;
     const double inv_h2 = (double)NN * (double)NN;
     gcdp e = (gcdp)e_;
@@ -219,7 +295,6 @@ __device__ __noinline__ double strip_residual(const double* e_, const double* xo
     __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
     const int i = c + 1;
     const bool colin = c < NN - 1;
-    const int cE = min(c + 1, NN - 1), cW = max(c - 1, 0), iE = min(i + 1, NN);
     double acc = 0.0;
     if (zero_x) {
 #pragma unroll 8
@@ -233,6 +308,13 @@ __device__ __noinline__ double strip_residual(const double* e_, const double* xo
         }
         return acc;
     }
+    const int lane = threadIdx.x & 63;
+    const int c0 = __builtin_amdgcn_readfirstlane(c - lane);       // first column of the wave
+    const int ieE = min(c0 + 65, NN), ieW = c0;                     // e columns beyond the wave's edges
+    const int cxE = min(c0 + 64, NN - 1), cxW = max(c0 - 1, 0);     // x columns beyond the edges
+    const bool xEok = c0 + 64 < NN - 1, xWok = c0 > 0;
+    gcdp eu = (gcdp)wave_uniform(e_);
+    const int g0u = __builtin_amdgcn_readfirstlane(g0);
     double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
     double xS = xo[max(g0 - 1, 0) * NN + c], xC = xo[g0 * NN + c];
     xS = (g0 > 0 && colin) ? xS : 0.0;
@@ -241,28 +323,32 @@ __device__ __noinline__ double strip_residual(const double* e_, const double* xo
     static_assert(R % B == 0, "strip blocking");
 #pragma unroll 1
     for (int r0 = 0; r0 < R; r0 += B) {
-        double eN[B], eE[B], eW[B], xN[B], xE[B], xW[B], sdv[B];
+        double eN[B], xN[B], sdv[B], eEe[B], eWe[B], xEe[B], xWe[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int g = g0 + r0 + k, j = g + 1;
             eN[k] = e[min(j + 1, NN) * NP1 + i];
-            eE[k] = e[j * NP1 + iE];
-            eW[k] = e[j * NP1 + i - 1];
             xN[k] = xo[min(g + 1, NN - 1) * NN + c];
-            xE[k] = xo[g * NN + cE];
-            xW[k] = xo[g * NN + cW];
             sdv[k] = sd[g * NN + c];
+            const int ju = g0u + r0 + k + 1;
+            eEe[k] = eu[ju * NP1 + ieE];
+            eWe[k] = eu[ju * NP1 + ieW];
+            xEe[k] = xo[g * NN + cxE];
+            xWe[k] = xo[g * NN + cxW];
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int r = r0 + k, g = g0 + r, j = g + 1;
+            const double eE = from_next_lane(eC, eEe[k]);
+            const double eW = from_prev_lane(eC, eWe[k]);
+            const double xe_ = from_next_lane(xC, xEok ? xEe[k] : 0.0);
+            const double xw_ = from_prev_lane(xC, xWok ? xWe[k] : 0.0);
             const double xn = (g + 1 < NN - 1 && colin) ? xN[k] : 0.0;
-            const double xe = (c + 1 < NN - 1) ? xE[k] : 0.0;
-            const double xw = (c > 0) ? xW[k] : 0.0;
+            const double xe = (c + 1 < NN - 1) ? xe_ : 0.0;
+            const double xw = (c > 0) ? xw_ : 0.0;
             const bool in = colin && g < NN - 1;
             const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
-            const double res =
-                fr - eC * inv_h2 * (eE[k] * (xC - xe) + eW[k] * (xC - xw) + eN[k] * (xC - xn) + eS * (xC - xS));
+            const double res = fr - eC * inv_h2 * (eE * (xC - xe) + eW * (xC - xw) + eN[k] * (xC - xn) + eS * (xC - xS));
             acc += in ? res * res : 0.0;
             tb[NN + 1 + r * NN] = in ? (T)(sdv[k] * res) : T(0);
             eS = eC;
@@ -300,31 +386,37 @@ __device__ __noinline__ void strip_update(double* xo_, const double* sd_, const 
 
 // D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots.
 template <typename T, int NN, int R>
-__device__ __noinline__ void strip_setup(const double* e_, double* sd_, T* tb_, int c, int g0) {
+__device__ __noinline__ void strip_setup(const double* __restrict__ e_, double* __restrict__ sd_, T* __restrict__ tb_,
+                                         int c, int g0) {
+    static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
     constexpr int NP1 = NN + 1;
     const double h = 1.0 / NN;
     gcdp e = (gcdp)e_;
     gdp sd = (gdp)sd_;
     __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
     const int i = c + 1;
-    const int iE = min(i + 1, NN);
+    const int lane = threadIdx.x & 63;
+    const int c0 = __builtin_amdgcn_readfirstlane(c - lane);
+    const int ieE = min(c0 + 65, NN), ieW = c0;
+    gcdp eu = (gcdp)wave_uniform(e_);
+    const int g0u = __builtin_amdgcn_readfirstlane(g0);
     double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
     constexpr int B = R < 8 ? R : 8;
 #pragma unroll 1
     for (int r0 = 0; r0 < R; r0 += B) {
-        double eN[B], eE[B], eW[B];
+        double eN[B], eEe[B], eWe[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            const int j = g0 + r0 + k + 1;
+            const int j = g0 + r0 + k + 1, ju = g0u + r0 + k + 1;
             eN[k] = e[min(j + 1, NN) * NP1 + i];
-            eE[k] = e[j * NP1 + iE];
-            eW[k] = e[j * NP1 + i - 1];
+            eEe[k] = eu[ju * NP1 + ieE];
+            eWe[k] = eu[ju * NP1 + ieW];
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int r = r0 + k, g = g0 + r, j = g + 1;
             const bool in = c < NN - 1 && g < NN - 1;
-            const double S = eE[k] + eW[k] + eN[k] + eS;
+            const double S = from_next_lane(eC, eEe[k]) + from_prev_lane(eC, eWe[k]) + eN[k] + eS;
             sd[g * NN + c] = in ? h / sqrt(eC * S) : 1.0;
             tb[NN + 1 + r * NN] = in ? (T)sqrt(eC / S) : T(0);
             eS = eC;
@@ -344,7 +436,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     constexpr int NP1 = NN + 1;
     constexpr int PAD = NN + 1;
     using DS = DstShape<NN, NW>;
-    static_assert(!DST || (NN >= 32 && (DS::NB * DS::NB) % NW == 0 && NW % DS::NB == 0), "transform tiling");
+    static_assert(!DST || NN >= 32, "transform tiling");
     static_assert(NW <= 16, "reduction slots");
     // FP64 passes as separate, unrolled functions (wide strips); inline loops otherwise
     constexpr bool SPLIT = R >= 32;
@@ -652,7 +744,6 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
 // writes them transposed.  The second pass applies 1 / (lam_i + lam_j); the fourth writes z (FP32).
 constexpr int D256_LD = 256 + 8;
 constexpr int D256_BYTES = 256 * D256_LD * 2;
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, __bf16* X,
                                              const __bf16* __restrict__ S, const float* __restrict__ lam) {
