@@ -46,7 +46,7 @@ def measured_traffic(tile):
         return None
 
 
-def cpu_baseline(d, sample_per_worker=40):
+def cpu_baseline(d, sample_per_worker=100):
     """The oracle, as it stands, on a bounded sample of the workload: `workers` processes each
     run one pCN-GM move for `sample_per_worker` particles (one sparse direct solve each)."""
     import concurrent.futures

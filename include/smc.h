@@ -256,7 +256,9 @@ int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, f
  * same solution up to rounding (the reduction order changes).
  *   smc_tile_candidates  the shapes the library has for grid n (rows[8] out, *count out);
  *                        the first is the default; grid 256 has the single entry 0
- *   smc_set_tile         choose one for grid `level` (0 = default); smc_get_tile reads it back
+ *   smc_set_tile         choose one for grid `level` (0 = default); smc_get_tile reads it back.
+ *                        The default of the forward-and-adjoint solve (smc_value_and_grad,
+ *                        smc_pcnl_move) at 128^2 is 16 rows; a shape set here applies to both
  *   smc_autotune         time every candidate on N synthetic prior particles (drawn by the
  *                        library into its own workspace), reps timed launches each after one
  *                        warm-up, keep the fastest; *rows out, ms[count] out (may be NULL): mean
