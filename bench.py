@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--moves", type=int, default=N_MOVES, help="moves per stage (profiling runs use fewer)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="rows per thread of the 128^2 solver (0: autotune before timing)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB device-to-device, to calibrate memory-traffic counters")
     args = ap.parse_args()
@@ -181,7 +183,11 @@ def main():
     torch.cuda.set_device(dev)
     p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-5)
     unknowns = (GRID - 1) ** 2
-    tile, tile_ms = smc.smc_autotune(p, 0, N, reps=2)      # tile shape of the solver, before timing
+    if args.tile:
+        smc.smc_set_tile(p, 0, args.tile)
+        tile, tile_ms = args.tile, {}
+    else:
+        tile, tile_ms = smc.smc_autotune(p, 0, N, reps=2)  # tile shape of the solver, before timing
 
     def stage_loop(prec, steps, warmup, n_moves):
         s = SMCSampler(p, N, M, n_moves, ess_frac=0.5, beta0=0.2, prec=prec, seed=2503, device=dev)
