@@ -745,15 +745,18 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
 constexpr int D256_LD = 256 + 8;
 constexpr int D256_BYTES = 256 * D256_LD * 2;
 
+// With `staged`, X already holds bf16(r) (written by the caller's residual update); with `rz`,
+// the thread's share of sum r z is accumulated while z is stored.
 __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, __bf16* X,
-                                             const __bf16* __restrict__ S, const float* __restrict__ lam) {
+                                             const __bf16* __restrict__ S, const float* __restrict__ lam,
+                                             bool staged = false, double* rz = nullptr) {
     constexpr int NN = 256, LD = D256_LD, KS = 8, NB = 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4, cb = wave;
     bf8 sB[KS];   // B operand: S[k][16 cb + lr] = S[16 cb + lr][k] (S is symmetric)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) sB[ks] = *reinterpret_cast<const bf8*>(S + (16 * cb + lr) * NN + 32 * ks + 8 * lk);
-    for (int e = tid; e < NN * NN / 8; e += 1024) {   // X = bf16(r), row-major
+    for (int e = staged ? NN * NN : tid; e < NN * NN / 8; e += 1024) {   // X = bf16(r), row-major
         const int g = e >> 5, c0 = (e & 31) * 8;
         const float4 u0 = *reinterpret_cast<const float4*>(r + g * NN + c0);
         const float4 u1 = *reinterpret_cast<const float4*>(r + g * NN + c0 + 4);
@@ -778,8 +781,13 @@ __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float*
                 for (int v = 0; v < 4; ++v) acc[v] *= __builtin_amdgcn_rcpf(lam[16 * ra + 4 * lk + v] + lam_c);
             }
             if (step == 3) {   // z[j][i] = P[i][j]
-                *reinterpret_cast<float4*>(z + (16 * cb + lr) * NN + 16 * ra + 4 * lk) =
-                    make_float4(acc[0], acc[1], acc[2], acc[3]);
+                const int at = (16 * cb + lr) * NN + 16 * ra + 4 * lk;
+                *reinterpret_cast<float4*>(z + at) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                if (rz) {
+                    const float4 rv4 = *reinterpret_cast<const float4*>(r + at);
+                    *rz += (double)rv4.x * (double)acc[0] + (double)rv4.y * (double)acc[1] +
+                           (double)rv4.z * (double)acc[2] + (double)rv4.w * (double)acc[3];
+                }
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) out[ra][v] = (__bf16)acc[v];
@@ -942,6 +950,79 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             }
             const double target = a.tol_inner * a.tol_inner * rr;
             bool broke = false;
+            if constexpr (DST) {
+                // Per iteration four passes over the global vectors: the stencil (t p of the
+                // neighbours formed on the fly), the x/r update (which also stages bf16(r) for the
+                // transform in LDS), the transform (z stored, r.z accumulated), the p update.
+                while (rr > target) {
+                    if (total >= a.max_iter) break;
+                    T pq_acc = T(0);
+                    for (int k = 4 * tid; k < nodes; k += 4096) {   // four consecutive nodes of a row
+                        const int g = k / NN, c = k % NN;
+                        const int kN = (g < NN - 1) ? k + NN : k, kS = (g > 0) ? k - NN : k;
+                        const int kW = (c > 0) ? k - 1 : k, kE = min(k + 4, nodes - 1);
+                        const float4 p4 = *reinterpret_cast<const float4*>(pv + k);
+                        const float4 t4 = *reinterpret_cast<const float4*>(tv + k);
+                        const float4 pN = *reinterpret_cast<const float4*>(pv + kN);
+                        const float4 tN = *reinterpret_cast<const float4*>(tv + kN);
+                        const float4 pS = *reinterpret_cast<const float4*>(pv + kS);
+                        const float4 tS = *reinterpret_cast<const float4*>(tv + kS);
+                        const float yW0 = (c > 0) ? tv[kW] * pv[kW] : 0.f, yE3 = tv[kE] * pv[kE];
+                        const float p_[4] = {p4.x, p4.y, p4.z, p4.w}, t_[4] = {t4.x, t4.y, t4.z, t4.w};
+                        const float pn[4] = {pN.x, pN.y, pN.z, pN.w}, tn[4] = {tN.x, tN.y, tN.z, tN.w};
+                        const float ps[4] = {pS.x, pS.y, pS.z, pS.w}, ts[4] = {tS.x, tS.y, tS.z, tS.w};
+                        float yc[4], q_[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) yc[m] = t_[m] * p_[m];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const float yE = (m < 3) ? yc[m < 3 ? m + 1 : 3] : yE3;
+                            const float yW = (m > 0) ? yc[m > 0 ? m - 1 : 0] : yW0;
+                            const float yN = tn[m] * pn[m];
+                            const float yS = (g > 0) ? ts[m] * ps[m] : 0.f;
+                            q_[m] = interior(g, c + m) ? p_[m] - t_[m] * ((yE + yW) + (yN + yS)) : 0.f;
+                            pq_acc += p_[m] * q_[m];
+                        }
+                        *reinterpret_cast<float4*>(qv + k) = make_float4(q_[0], q_[1], q_[2], q_[3]);
+                    }
+                    const double pq = block_sum<NW>((double)pq_acc, red1);
+                    if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
+                    const T alpha = (T)(rz / pq);
+                    T r_acc = T(0);
+                    for (int k = 4 * tid; k < nodes; k += 4096) {
+                        float4 x4 = *reinterpret_cast<const float4*>(xv + k);
+                        const float4 p4 = *reinterpret_cast<const float4*>(pv + k);
+                        float4 r4 = *reinterpret_cast<const float4*>(rv + k);
+                        const float4 q4 = *reinterpret_cast<const float4*>(qv + k);
+                        x4.x += alpha * p4.x; x4.y += alpha * p4.y; x4.z += alpha * p4.z; x4.w += alpha * p4.w;
+                        r4.x -= alpha * q4.x; r4.y -= alpha * q4.y; r4.z -= alpha * q4.z; r4.w -= alpha * q4.w;
+                        r_acc += ((r4.x * r4.x + r4.y * r4.y) + (r4.z * r4.z + r4.w * r4.w));
+                        *reinterpret_cast<float4*>(xv + k) = x4;
+                        *reinterpret_cast<float4*>(rv + k) = r4;
+                        bf4 b;
+                        b[0] = (__bf16)r4.x; b[1] = (__bf16)r4.y; b[2] = (__bf16)r4.z; b[3] = (__bf16)r4.w;
+                        *reinterpret_cast<bf4*>(X + (k / NN) * D256_LD + (k % NN)) = b;
+                    }
+                    rr = block_sum<NW>((double)r_acc, red2);   // its barrier also publishes X
+                    ++total;
+                    if (!(rr > target)) break;
+                    double zacc = 0.0;
+                    dst256_apply(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), X, Stab, lamtab,
+                                 true, &zacc);
+                    ++napp;
+                    const double rzn = block_sum<NW>(zacc, red1);
+                    const T beta = (T)(rzn / rz);
+                    rz = rzn;
+                    for (int k = 4 * tid; k < nodes; k += 4096) {
+                        const float4 z4 = *reinterpret_cast<const float4*>(zv + k);
+                        float4 p4 = *reinterpret_cast<const float4*>(pv + k);
+                        p4.x = z4.x + beta * p4.x; p4.y = z4.y + beta * p4.y;
+                        p4.z = z4.z + beta * p4.z; p4.w = z4.w + beta * p4.w;
+                        *reinterpret_cast<float4*>(pv + k) = p4;
+                    }
+                    __syncthreads();
+                }
+            } else {
             while (rr > target) {
                 if (total >= a.max_iter) break;
                 for (int k = tid; k < nodes; k += 1024) yv[k] = tv[k] * pv[k];
@@ -973,22 +1054,11 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                 }
                 const double rrn = block_sum<NW>((double)r_acc, red2);
                 ++total;
-                if constexpr (DST) {
-                    rr = rrn;
-                    if (!(rr > target)) break;
-                    precondition();
-                    double zacc = 0.0;
-                    for (int k = tid; k < nodes; k += 1024) zacc += (double)rv[k] * (double)zv[k];
-                    const double rzn = block_sum<NW>(zacc, red1);
-                    const T beta = (T)(rzn / rz);
-                    rz = rzn;
-                    for (int k = tid; k < nodes; k += 1024) pv[k] = zv[k] + beta * pv[k];
-                } else {
-                    const T beta = (T)(rrn / rr);
-                    rr = rrn;
-                    rz = rr;
-                    for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
-                }
+                const T beta = (T)(rrn / rr);
+                rr = rrn;
+                rz = rr;
+                for (int k = tid; k < nodes; k += 1024) pv[k] = rv[k] + beta * pv[k];
+            }
             }
             for (int k = tid; k < nodes; k += 1024) {
                 const double corr = sd[k] * (double)xv[k];
