@@ -15,8 +15,8 @@ Modules
   moves      pCN, pCN-GM (Sec. 2.3, Alg. 2) and pCN-Langevin moves, MH acceptance
   temper     ESS bisection of the next temperature (App. C)
   resample   systematic resampling with an exact integer CDF (Alg. 1, resampling)
-  gmfit      diagonal Gaussian-mixture EM used as the stage input (parity unpinned)
-  smc        the SMC loop of Alg. 1 with the pCN-GM mutation (SMC-pCN-GM)
+  gmfit      diagonal Gaussian-mixture EM with k-means++ seeding (the stage input)
+  smc        the SMC loop of Alg. 1 with the pCN-GM mutation (SMC-pCN-GM) and SMC-GM (Alg. 3)
   adjoint    gradient of the potential by an adjoint solve
   linear     closed-form linear-Gaussian posterior (test target)
   quadrature brute-force posterior moments for tiny problems (test target)

@@ -105,6 +105,24 @@ def propose_gmpcn(gm, beta, xi, z, u_comp):
     return gamma * xi + (1.0 - gamma) * m[j] + beta * np.sqrt(s[j]) * z, j
 
 
+def gm_draw(gm, seed, ctr, ids):
+    """Independent draws from the mixture, the mutation of SMC-GM (Alg. 3): the pCN-GM
+    proposal with beta = 1 (Sec. 2.4, eq. (GMM beta=1)), where gamma = 0 removes the
+    current state.  Component j = min{j : sum_{i<=j} w_i > U_comp} (U_comp of block
+    UNIFORM_BLOCK), then v = m_j + sqrt(s_j) z on the active modes and v = z elsewhere,
+    with z the particle's normals at counter ctr."""
+    ids = np.asarray(ids, dtype=np.int64)
+    z = philox.normals(seed, ctr, ids, gm.K)
+    uc, _ = philox.move_uniforms(seed, ctr, ids)
+    m, s = gm.full()
+    cum = np.cumsum(np.exp(gm.logw))
+    v = np.empty_like(z)
+    for p in range(ids.size):
+        j = min(int(np.searchsorted(cum, uc[p], side="right")), gm.M - 1)
+        v[p] = m[j] + np.sqrt(s[j]) * z[p]
+    return v
+
+
 def gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, ctr, phi_fn=None, ids=None):
     """n_moves pCN-GM steps (Alg. 2) for every particle; returns (xi, phi, n_acc).
 

@@ -1,4 +1,4 @@
-"""The SMC loop of Alg. 1 with a pCN-GM mutation (SMC-pCN-GM).
+"""The SMC loop of Alg. 1 with a pCN-GM mutation (SMC-pCN-GM), and SMC-GM (Alg. 3).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -11,14 +11,22 @@ finally the App. C step-size rule
 capped at beta <= 1 since the proposal needs beta in (0, 1] (Sec. 2.3).
 The loop stops when the cumulative temperature reaches 1 (sum_j h_j = 1).
 
+SMC-GM (Alg. 3, Sec. 2.4) keeps the re-weighting and resampling and replaces the
+mutation by the mixture itself: fit the mixture to the resampled cloud, replace every
+particle by an independent draw from it (accepted without a test), and evaluate the
+potential of the draws, which the next stage re-weights.  The loop stops after the
+stage whose temperature reaches 1 (Alg. 3 runs its loop one step further than Alg. 1;
+both stop at the same final temperature here).
+
 Random numbers: the prior draw uses counter 0; stage s uses counters
 s * 2^20 + m for its moves and draws its resampling uniform from block
-RESAMPLE_BLOCK at counter s * 2^20.
+RESAMPLE_BLOCK at counter s * 2^20.  SMC-GM's fit and draw at stage s both use
+counter s * 2^20 (different blocks).
 """
 import numpy as np
 
 from . import gmfit, philox
-from .moves import GM, gmpcn_moves, pcn_gm, prior_sample
+from .moves import GM, gm_draw, gmpcn_moves, pcn_gm, prior_sample
 from .resample import systematic
 from .temper import temper
 
@@ -72,3 +80,31 @@ def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stag
         if tau >= 1.0:
             break
     return dict(xi=xi, phi=phi, taus=np.array(taus), log_Z=log_Z, betas=betas, rates=rates)
+
+
+def run_gm(prob, n, N, M, rho, seed, phi_fn=None, kr=None, iters=50, var_floor=1e-3, max_stages=500):
+    """SMC-GM (Alg. 3).  Returns dict(xi, phi, taus, log_Z, mixtures)."""
+    from .forward import phi as phi_pde
+    K = prob.K
+    f = phi_fn if phi_fn is not None else (lambda x: phi_pde(prob, x, n))
+    active = prob.active() if kr is None else np.arange(kr)
+    xi = prior_sample(K, N, seed, 0)
+    phi = np.array([f(x) for x in xi])
+    tau, log_Z = 0.0, 0.0
+    taus, mixtures = [0.0], []
+    for s in range(1, max_stages + 1):
+        h, tau, W, lz, stalled = temper(phi, tau, rho)
+        if stalled:
+            raise RuntimeError("temperature bisection stalled")
+        log_Z += lz
+        taus.append(tau)
+        ctr = s * STAGE_STRIDE
+        idx = systematic(W, resample_u53(seed, ctr))
+        logw, mean, var, _ = gmfit.fit_philox(xi[idx][:, active], M, seed, ctr, iters, var_floor)
+        gm = GM(logw, mean, var, active, K)
+        mixtures.append((logw, mean, var))
+        xi = gm_draw(gm, seed, ctr, np.arange(N))
+        phi = np.array([f(x) for x in xi])
+        if tau >= 1.0:
+            break
+    return dict(xi=xi, phi=phi, taus=np.array(taus), log_Z=log_Z, mixtures=mixtures)

@@ -47,3 +47,17 @@ def weights(N, seed, kind="dirichlet"):
 
 def u53(seed):
     return int(np.random.default_rng(seed).integers(0, 2 ** 53))
+
+
+def clusters(N, D, M, seed, sep=4.0, dup=0):
+    """A cloud of N points in D dimensions around M random centres (spread `sep`), with
+    per-cluster, per-axis scales in [0.3, 1.2]; the last `dup` rows repeat row 0.
+    Returns (X, labels, centres, scales)."""
+    rng = np.random.default_rng(seed)
+    centres = sep * rng.standard_normal((M, D))
+    scales = rng.uniform(0.3, 1.2, (M, D))
+    labels = rng.integers(0, M, N)
+    X = centres[labels] + scales[labels] * rng.standard_normal((N, D))
+    if dup:
+        X[N - dup:] = X[0]
+    return X, labels, centres, scales
