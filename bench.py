@@ -207,9 +207,7 @@ def main():
             s.tau.copy_(s.tau_new)
             tau = float(s.tau.item())
             t1 = time.perf_counter()
-            X = s.xi.cpu().numpy()[:, p.active]          # stage input: mixture fit (not timed)
-            logw, mean, var = fit_mixture(X, M, s.seed + s.stage, iters=20)
-            gm = tuple(torch.tensor(a, dtype=torch.float64, device=dev).contiguous() for a in (logw, mean, var))
+            gm = fit_mixture(p, N, s.xi, M, s.seed, s.stage << 20)   # stage input: mixture fit (not timed)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             smc.smc_gmpcn_move(p, N, gm, s.beta, tau, n_moves, s.seed, s.stage << 20, None, prec, s.xi, s.phi,

@@ -221,6 +221,41 @@ int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, int32_t n_m
                   uint64_t ctr, int32_t prec, double* xi, double* phi, double* grad, int32_t* n_acc,
                   smc_stream stream);
 
+/* SMC-GM mutation (Alg. 3, Sec. 2.4): N independent draws from the mixture, each accepted, and
+ * their potentials.  The draw is the pCN-GM proposal with beta = 1 (eq. (GMM beta=1)):
+ *   v = m_j + sqrt(s_j) z on the active modes, v = z elsewhere, z ~ N(0, I),
+ *   component j = min{j : w_1 + ... + w_j > U_comp},
+ * with the normals and U_comp that a pCN-GM move of the same particle draws at counter ctr.
+ *   xi  [N][K] out (the draws; no input state), phi [N] out (+inf where the solve does not
+ *       converge), iters [N] out or NULL; level: grid of each particle or NULL (grid 0).
+ * The caller owns every array; gm's arrays are read on the device during the call's kernels. */
+int smc_gm_draw(smc_problem p, int64_t N, const smc_gm* gm, uint64_t seed, uint64_t ctr,
+                const int32_t* level, int32_t prec, double* xi, double* phi, int32_t* iters,
+                smc_stream stream);
+
+/* Gaussian-mixture fit of a particle cloud on the device: the stage input of the pCN-GM move
+ * (Sec. 2.3) and of SMC-GM (Sec. 2.4, Alg. 3).  The paper's estimator (its reference [Feng2018])
+ * is not described there; this is EM with diagonal covariances on the problem's K_r active
+ * whitened coordinates of xi[0..N):
+ *   seeding  k-means++: centre 0 is row floor(u_0 N / 2^53); centre m >= 1 is row
+ *            min{n : C_n > floor(u_m Q / 2^53)}, where C_n = sum_{i<=n} q_i, Q = C_{N-1},
+ *            q_i = floor(d2_i 2^(40-e)), d2_i the squared distance of row i to its nearest
+ *            centre (coordinates summed in pairwise order over 64 zero-padded slots),
+ *            max_i d2_i = f 2^e with f in [1/2, 1); row floor(u_m N / 2^53) if Q = 0.  u_m is
+ *            the 53-bit integer (w0 >> 5) 2^26 + (w1 >> 6) of Philox block 0x80000002,
+ *            particle word m, counter ctr.  The choice is exact integer arithmetic.
+ *   start    w_j = 1/M, m_j = the seeded rows, s_j = max(variance of the cloud, var_floor);
+ *   EM       `iters` steps: responsibilities in log space, then w_j = N_j / N,
+ *            m_j = sum R x / N_j, s_j = max(sum R x^2 / N_j - m_j^2, var_floor),
+ *            N_j = sum_n R_nj + 1e-300; partial sums are added in a fixed order.
+ *   out: logw [M] (normalised), mean [M][kr], scale [M][kr] (the variances s_j, the smc_gm
+ *   scale), centers [M] (the seeded rows; may be NULL).  1 <= N <= min(n_max, 2^24),
+ *   1 <= M <= 16, 0 <= iters <= 100000, var_floor > 0.  Calls on one problem share its
+ *   workspace: do not run two on different streams at once. */
+int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M, int32_t iters, double var_floor,
+               uint64_t seed, uint64_t ctr, double* logw, double* mean, double* scale, int32_t* centers,
+               smc_stream stream);
+
 /* Re-weighting and next temperature (Alg. 1; App. C): with tau = *tau_in (device scalar),
  * choose h in (0, 1 - tau] by 64 bisection steps keeping ESS(h) >= ess_frac * N, where
  * ESS = 1 / sum W^2 and W_n ∝ exp(-h Phi_n); take h = 1 - tau when that already passes.

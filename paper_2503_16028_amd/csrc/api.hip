@@ -63,6 +63,7 @@ static void free_problem(Problem& P) {
     f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_lam); f(P.ws_gnew); f(P.ws_sd);
     f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.ws_list); f(P.ws_counters); f(P.flags); f(P.stats);
+    f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers); f(P.ws_fit_counter);
 }
 
 extern "C" const char* smc_last_error(void) { return g_err.c_str(); }
@@ -218,6 +219,15 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     ck(hipMalloc((void**)&P.ws_list, sizeof(int32_t) * Nm));
     ck(hipMalloc((void**)&P.ws_counters, 2 * sizeof(unsigned long long)));
     ck(hipMemset(P.ws_counters, 0, 2 * sizeof(unsigned long long)));
+    {
+        const size_t pe = (size_t)MAX_M * (1 + 2 * MAX_KR);
+        ck(hipMalloc((void**)&P.ws_fit_d2, sizeof(double) * Nm));
+        ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * pe));
+        ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * pe));
+        ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
+        ck(hipMalloc((void**)&P.ws_fit_counter, sizeof(unsigned int)));
+        ck(hipMemset(P.ws_fit_counter, 0, sizeof(unsigned int)));
+    }
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
     ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
@@ -559,15 +569,62 @@ static int check_move_common(const Problem& P, int64_t N, int32_t n_moves, const
     return SMC_OK;
 }
 
+static int check_gm(const Problem& P, const smc_gm* gm) {
+    if (!gm) return fail(SMC_E_INVAL, "gm is NULL");
+    if (gm->M < 1 || gm->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (gm->kr != P.kr) return fail(SMC_E_INVAL, "gm.kr (%d) differs from the problem's kr (%d)", gm->kr, P.kr);
+    if (!gm->logw || !gm->mean || !gm->scale) return fail(SMC_E_INVAL, "mixture arrays must not be NULL");
+    return SMC_OK;
+}
+
+extern "C" int smc_gm_draw(smc_problem p, int64_t N, const smc_gm* gm, uint64_t seed, uint64_t ctr,
+                           const int32_t* level, int32_t prec, double* xi, double* phi, int32_t* iters,
+                           smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (int r = check_gm(P, gm)) return r;
+    if (int r = check_n(P, N)) return r;
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (level)
+        if (int r = check_levels(P)) return r;
+    if (N > 0 && (!xi || !phi)) return fail(SMC_E_INVAL, "xi and phi must not be NULL");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    if (N == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_gm_draw(N, P.K, P.slot, seed, ctr, gm->M, gm->kr, gm->logw, gm->mean, gm->scale, xi, s));
+    if (level) HIPCHK(launch_plan(N, level, level_table(P), P.ws_list, P.ws_counters, P.flags, s));
+    Solve o;
+    o.level = level;
+    o.phi = phi;
+    o.iters = iters ? iters : P.ws_iters;
+    HIPCHK(forward(p, 0, prec, N, xi, o, s));
+    return SMC_OK;
+}
+
+extern "C" int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M, int32_t iters, double var_floor,
+                          uint64_t seed, uint64_t ctr, double* logw, double* mean, double* scale, int32_t* centers,
+                          smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (int r = check_n(P, N)) return r;
+    if (N < 1) return fail(SMC_E_INVAL, "the fit needs at least one particle");
+    if (N > (1ll << 24)) return fail(SMC_E_INVAL, "the fit takes at most 2^24 particles");
+    if (M < 1 || M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (iters < 0 || iters > 100000) return fail(SMC_E_INVAL, "iters must be 0..100000");
+    if (!(var_floor > 0.0) || !std::isfinite(var_floor)) return fail(SMC_E_INVAL, "var_floor must be positive");
+    if (!xi || !logw || !mean || !scale) return fail(SMC_E_INVAL, "xi, logw, mean and scale must not be NULL");
+    FitWorkspace w{P.ws_fit_d2, P.ws_fit_par, P.ws_fit_part, P.ws_fit_counter};
+    HIPCHK(launch_gm_fit(N, P.K, P.kr, P.active, xi, M, iters, var_floor, seed, ctr, w,
+                         centers ? centers : P.ws_fit_centers, logw, mean, scale, (hipStream_t)stream));
+    return SMC_OK;
+}
+
 extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
                               int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level, int32_t prec,
                               double* xi, double* phi, int32_t* n_acc, smc_stream stream) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
     const Problem& P = p->P;
-    if (!gm) return fail(SMC_E_INVAL, "gm is NULL");
-    if (gm->M < 1 || gm->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
-    if (gm->kr != P.kr) return fail(SMC_E_INVAL, "gm.kr (%d) differs from the problem's kr (%d)", gm->kr, P.kr);
-    if (!gm->logw || !gm->mean || !gm->scale) return fail(SMC_E_INVAL, "mixture arrays must not be NULL");
+    if (int r = check_gm(P, gm)) return r;
     if (!(beta > 0.0 && beta <= 1.0)) return fail(SMC_E_INVAL, "beta must be in (0, 1]");
     if (!(tau >= 0.0 && tau <= 1.0)) return fail(SMC_E_INVAL, "tau must be in [0, 1]");
     if (int r = check_move_common(P, N, n_moves, level, prec, xi, phi, n_acc)) return r;

@@ -49,6 +49,11 @@ struct Problem {
     int32_t* ws_iters = nullptr; // [n_max]
     int32_t* ws_list = nullptr;  // [n_max] work list of a level map (particles grouped by grid)
     unsigned long long* ws_counters = nullptr;   // [2] work and exit counters of the persistent solve
+    double* ws_fit_d2 = nullptr;      // [n_max]   squared distance to the nearest seeded centre
+    double* ws_fit_par = nullptr;     // [2][MAX_M][1 + 2 MAX_KR]  EM parameters (ping-pong)
+    double* ws_fit_part = nullptr;    // [em blocks][MAX_M][1 + 2 MAX_KR]  EM partial sums
+    int32_t* ws_fit_centers = nullptr;  // [MAX_M] seeded rows
+    unsigned int* ws_fit_counter = nullptr;   // workgroups done in the current EM launch
     int n_cu = 0;                // compute units of the device
     int32_t* flags = nullptr;    // device status word
     unsigned long long* stats = nullptr;  // [4] iterations, sweeps, solves, preconditioner applications
@@ -234,6 +239,20 @@ hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t
 hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
                          const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s);
 hipError_t prepare_kernels();
+hipError_t launch_gm_draw(int64_t N, int K, const int32_t* slot, uint64_t seed, uint64_t ctr, int M, int kr,
+                          const double* logw, const double* mean, const double* scale, double* v, hipStream_t s);
+
+struct FitWorkspace {
+    double* d2;
+    double* par;
+    double* part;
+    unsigned int* counter;
+};
+int64_t em_blocks(int64_t N);
+hipError_t prepare_gmfit_kernels();
+hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                         double var_floor, uint64_t seed, uint64_t ctr, const FitWorkspace& w, int32_t* centers,
+                         double* logw, double* mean, double* scale, hipStream_t s);
 hipError_t launch_gather(int64_t N, int K, const int32_t* idx, const double* xi_in, const double* phi_in,
                          double* xi_out, double* phi_out, hipStream_t s);
 hipError_t launch_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,

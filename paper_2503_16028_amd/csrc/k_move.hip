@@ -59,6 +59,20 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Mixture component of particle n: j = min{j : w_0 + ... + w_j > U_comp} (U_comp from words 0, 1
+// of block UNIFORM_BLOCK at counter ctr), the last component if rounding leaves the sum below U.
+__device__ __forceinline__ int choose_component(uint64_t seed, uint64_t ctr, int64_t n, int M,
+                                                const double* __restrict__ logw) {
+    const uint4 w = draw(seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+    const double uc = res53(w.x, w.y);
+    double cum = 0.0;
+    for (int m = 0; m < M; ++m) {
+        cum += exp(logw[m]);
+        if (cum > uc) return m;
+    }
+    return M - 1;
+}
+
 // pCN-GM proposal (Sec. 2.3, eq. (pCN-GM proposal), component-wise) and its log ratio.
 //
 // The Metropolis-Hastings ratio rho(dv) Q(v, dxi) / (rho(dxi) Q(xi, dv)) of eq. (auv of
@@ -97,17 +111,7 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __re
     const double* scale = q.scale + (int64_t)grp * M * kr;
     const uint64_t ctr = mp_ctr(q);
     const double gamma = sqrt(1.0 - beta * beta);
-    if (threadIdx.x == 0) {
-        const uint4 w = draw(q.seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
-        const double uc = res53(w.x, w.y);
-        double cum = 0.0;
-        int j = M - 1;
-        for (int m = 0; m < M; ++m) {
-            cum += exp(logw[m]);
-            if (cum > uc) { j = m; break; }
-        }
-        comp = j;
-    }
+    if (threadIdx.x == 0) comp = choose_component(q.seed, ctr, n, M, logw);
     __syncthreads();
     const int j = comp;
     const int nb = (K + 1) / 2;
@@ -166,6 +170,41 @@ hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t
                           const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     propose_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
+    return hipGetLastError();
+}
+
+// Independent draws from the mixture, the mutation of SMC-GM (Alg. 3): the pCN-GM proposal with
+// beta = 1 (Sec. 2.4, eq. (GMM beta=1)), where gamma = 0 drops the current state, so
+// v = m_j + sqrt(s_j) z on the active modes and v = z elsewhere; the component and the normals are
+// the ones a pCN-GM move of the same particle would draw at this counter.
+__global__ __launch_bounds__(256) void gm_draw_kernel(int K, const int32_t* __restrict__ slot, uint64_t seed,
+                                                      uint64_t ctr, int M, int kr, const double* __restrict__ logw,
+                                                      const double* __restrict__ mean,
+                                                      const double* __restrict__ scale, double* __restrict__ v) {
+    __shared__ int comp;
+    const int64_t n = blockIdx.x;
+    if (threadIdx.x == 0) comp = choose_component(seed, ctr, n, M, logw);
+    __syncthreads();
+    const int j = comp;
+    double* vp = v + n * K;
+    const int nb = (K + 1) / 2;
+    for (int blk = threadIdx.x; blk < nb; blk += 256) {
+        double z[2];
+        box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * blk + h;
+            if (k >= K) break;
+            const int sl = slot[k];
+            vp[k] = sl >= 0 ? mean[j * kr + sl] + sqrt(scale[j * kr + sl]) * z[h] : z[h];
+        }
+    }
+}
+
+hipError_t launch_gm_draw(int64_t N, int K, const int32_t* slot, uint64_t seed, uint64_t ctr, int M, int kr,
+                          const double* logw, const double* mean, const double* scale, double* v, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    gm_draw_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, slot, seed, ctr, M, kr, logw, mean, scale, v);
     return hipGetLastError();
 }
 

@@ -249,6 +249,7 @@ hipError_t prepare_kernels() {
     ck(hipFuncSetAttribute((const void*)synth2d_levels_kernel<true>, A, synth));
     ck(hipFuncSetAttribute((const void*)synth2d_levels_kernel<false>, A, synth));
     ck(hipFuncSetAttribute((const void*)gradsynth2d_kernel, A, grad));
+    ck(prepare_gmfit_kernels());
     return e;
 }
 

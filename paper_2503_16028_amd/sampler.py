@@ -1,13 +1,16 @@
-"""SMC-pCN-GM driver: the loop of Alg. 1 with the pCN-GM mutation, over the C ABI.
+"""SMC drivers over the C ABI: SMC-pCN-GM (Alg. 1 with the pCN-GM mutation) and SMC-GM (Alg. 3).
 
-Per stage, in the order S^N P_{j+1} L_{j+1} of Sec. 2.2 (eq. (decidemuJN)):
+SMC-pCN-GM, per stage, in the order S^N P_{j+1} L_{j+1} of Sec. 2.2 (eq. (decidemuJN)):
   smc_temper    next increment h by ESS bisection (App. C), weights, log Z increment
   smc_resample  systematic resampling of the re-weighted cloud (Alg. 1)
   smc_gather    copy the selected rows
-  mixture fit   Gaussian mixture over the active modes (stage input, see fit_mixture)
+  smc_gm_fit    Gaussian mixture over the active modes (the stage input)
   smc_gmpcn_move  n_moves pCN-GM steps at the new temperature (Alg. 2)
   step size     beta <- 2 beta if acceptance > 0.3, beta / 2 if < 0.15 (App. C), beta <= 1
-The loop ends when the cumulative temperature reaches 1.
+SMC-GM replaces the moves by smc_gm_draw: every particle becomes an independent draw from the
+fitted mixture, accepted without a test, and its potential is what the next stage re-weights.
+Both loops end when the cumulative temperature reaches 1.  Every step runs on the device; the
+host reads back the temperature (and the acceptance count) once per stage.
 """
 import numpy as np
 import torch
@@ -17,36 +20,14 @@ from . import smc
 STAGE_STRIDE = 1 << 20
 
 
-def fit_mixture(X, M, seed, iters=50, var_floor=1e-3):
-    """Diagonal Gaussian mixture by EM on rows of X (host, float64).
-
-    The paper fits its mixture with the estimator of its reference [Feng2018], which it does
-    not describe; this stand-in seeds the means by k-means++ and runs a fixed number of EM
-    steps with a variance floor.  Returns (logw[M], mean[M][D], var[M][D]).
-    """
-    X = np.asarray(X, dtype=np.float64)
-    N, D = X.shape
-    rng = np.random.default_rng(seed)
-    centers = [X[rng.integers(N)]]
-    for _ in range(1, M):
-        d2 = np.min(np.stack([((X - c) ** 2).sum(1) for c in centers]), axis=0)
-        tot = d2.sum()
-        centers.append(X[rng.choice(N, p=d2 / tot)] if tot > 0 else X[rng.integers(N)])
-    mean = np.array(centers)
-    var = np.tile(np.maximum(X.var(0), var_floor), (M, 1))
-    logw = np.full(M, -np.log(M))
-    for _ in range(iters):
-        ll = logw[None, :] - 0.5 * (((X[:, None, :] - mean[None]) ** 2) / var[None] +
-                                    np.log(2 * np.pi * var[None])).sum(-1)
-        mx = ll.max(1, keepdims=True)
-        R = np.exp(ll - mx)
-        R /= R.sum(1, keepdims=True)
-        Nk = R.sum(0) + 1e-300
-        logw = np.log(Nk / N)
-        mean = (R.T @ X) / Nk[:, None]
-        var = np.maximum((R.T @ (X * X)) / Nk[:, None] - mean ** 2, var_floor)
-    logw -= np.log(np.exp(logw - logw.max()).sum()) + logw.max()
-    return logw, mean, var
+def fit_mixture(problem, N, xi, M, seed, ctr, iters=50, var_floor=1e-3):
+    """Device mixture fit of xi[0..N) (k-means++ then EM, smc_gm_fit): (logw, mean, scale)."""
+    f64 = dict(dtype=torch.float64, device=xi.device)
+    logw = torch.empty(M, **f64)
+    mean = torch.empty(M, problem.kr, **f64)
+    scale = torch.empty(M, problem.kr, **f64)
+    smc.smc_gm_fit(problem, N, xi, M, iters, var_floor, seed, ctr, logw, mean, scale)
+    return logw, mean, scale
 
 
 def pcn_mixture(kr, device):
@@ -58,8 +39,9 @@ def pcn_mixture(kr, device):
 
 class SMCSampler:
     def __init__(self, problem, N, M, n_moves, ess_frac=0.5, beta0=0.2, prec=smc.SMC_FP32_REFINE, seed=0,
-                 device="cuda"):
+                 device="cuda", fit_iters=50):
         self.p, self.N, self.M, self.n_moves = problem, int(N), int(M), int(n_moves)
+        self.fit_iters = int(fit_iters)
         self.ess_frac, self.beta, self.prec, self.seed = ess_frac, float(beta0), prec, int(seed)
         dev = torch.device(device)
         K = problem.K
@@ -92,10 +74,7 @@ class SMCSampler:
     def mixture(self):
         if self.M == 1:
             return pcn_mixture(self.p.kr, self.dev)
-        X = self.xi.cpu().numpy()[:, self.p.active]
-        logw, mean, var = fit_mixture(X, self.M, self.seed + self.stage)
-        t = lambda a: torch.tensor(a, dtype=torch.float64, device=self.dev).contiguous()
-        return t(logw), t(mean), t(var)
+        return fit_mixture(self.p, self.N, self.xi, self.M, self.seed, self.stage * STAGE_STRIDE, self.fit_iters)
 
     def step(self):
         """One stage: temper, resample, gather, mixture, moves, step-size rule."""
@@ -130,3 +109,32 @@ class SMCSampler:
         if int(self.flags.item()) & smc.FLAG_STALL:
             raise RuntimeError("temperature bisection stalled")
         return dict(xi=self.xi, phi=self.phi, log_Z=self.log_Z, history=self.history)
+
+
+class SMCGMSampler(SMCSampler):
+    """SMC-GM (Alg. 3): re-weight, resample, fit the mixture to the resampled cloud, replace every
+    particle by an independent draw from it (accepted without a test) and evaluate its potential.
+    Random numbers: stage s fits and draws at counter s * 2^20 (distinct Philox blocks)."""
+
+    def __init__(self, problem, N, M, ess_frac=0.5, prec=smc.SMC_FP32_REFINE, seed=0, device="cuda",
+                 fit_iters=50):
+        super().__init__(problem, N, M, 0, ess_frac=ess_frac, prec=prec, seed=seed, device=device,
+                         fit_iters=fit_iters)
+
+    def step(self):
+        p, N = self.p, self.N
+        self.stage += 1
+        base = self.stage * STAGE_STRIDE
+        smc.smc_temper(N, self.phi, self.tau, self.ess_frac, self.h, self.tau_new, self.W, self.log_z, self.flags)
+        u53 = int(np.random.default_rng([self.seed, self.stage]).integers(0, 1 << 53))
+        smc.smc_resample(N, self.W, u53, self.idx, self.flags)
+        smc.smc_gather(N, p.K, self.idx, self.xi, self.phi, self.xi2, self.phi2)
+        self.xi, self.xi2 = self.xi2, self.xi
+        self.tau.copy_(self.tau_new)
+        gm = fit_mixture(p, N, self.xi, self.M, self.seed, base, self.fit_iters)
+        smc.smc_gm_draw(p, N, gm, self.seed, base, None, self.prec, self.xi2, self.phi)
+        self.xi, self.xi2 = self.xi2, self.xi
+        tau = float(self.tau.item())
+        self.log_Z += float(self.log_z.item())
+        self.history.append(dict(stage=self.stage, tau=tau, h=float(self.h.item())))
+        return tau

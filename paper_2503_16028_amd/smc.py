@@ -58,6 +58,8 @@ _SIGS = {
     "smc_potential": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "smc_gmpcn_move": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_dbl, c_dbl, c_i32, c_u64, c_u64, c_vp, c_i32,
                                c_vp, c_vp, c_vp, c_vp]),
+    "smc_gm_draw": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_u64, c_u64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "smc_gm_fit": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_i32, c_dbl, c_u64, c_u64, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_forward_state": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_value_and_grad": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_pcnl_move": (c_i32, [c_vp, c_i64, c_dbl, c_dbl, c_i32, c_u64, c_u64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -225,6 +227,24 @@ def smc_gmpcn_move(problem, N, gm, beta, tau, n_moves, seed, ctr, level, prec, x
                                 ctr, _ptr(level, torch.int32, N, "level", optional=True), prec,
                                 _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
                                 _ptr(n_acc, torch.int32, N, "n_acc"), _stream(stream)))
+
+
+def smc_gm_draw(problem, N, gm, seed, ctr, level, prec, xi, phi, iters=None, stream=None):
+    """SMC-GM mutation: xi[N][K] <- independent mixture draws, phi[N] <- their potentials."""
+    d = gm_desc(*gm)
+    _check(lib().smc_gm_draw(problem.handle, N, ctypes.byref(d), seed, ctr,
+                             _ptr(level, torch.int32, N, "level", optional=True), prec,
+                             _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
+                             _ptr(iters, torch.int32, N, "iters", optional=True), _stream(stream)))
+
+
+def smc_gm_fit(problem, N, xi, M, iters, var_floor, seed, ctr, logw, mean, scale, centers=None, stream=None):
+    """Mixture fit of xi[0..N) on the active modes into logw[M], mean[M][kr], scale[M][kr]."""
+    kr = problem.kr
+    _check(lib().smc_gm_fit(problem.handle, N, _ptr(xi, torch.float64, N * problem.K, "xi"), int(M), int(iters),
+                            float(var_floor), seed, ctr, _ptr(logw, torch.float64, M, "logw"),
+                            _ptr(mean, torch.float64, M * kr, "mean"), _ptr(scale, torch.float64, M * kr, "scale"),
+                            _ptr(centers, torch.int32, M, "centers", optional=True), _stream(stream)))
 
 
 def smc_forward_state(problem, N, xi, prec, G, w, iters=None, stream=None):

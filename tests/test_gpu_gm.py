@@ -1,0 +1,248 @@
+"""SMC-GM on the GPU against the oracle: mixture fit, mixture draw and the whole Alg. 3 loop.
+
+  * smc_gm_fit: the seeded centres are integer decisions and must match the oracle's
+    (`gmfit.kmeanspp_philox`) exactly; the EM parameters from the same start match to 1e-9
+    relative (both FP64; only the order of the partial sums differs);
+  * smc_gm_draw: the draws match the oracle's (`moves.gm_draw`) to 1e-12 and their potentials
+    to 1e-9 (FP64 path) or 1e-4 (FP32 + refinement), as the move parity tests;
+  * SMCGMSampler: a whole run on the mirrored 1D problem against the oracle's run of Alg. 3
+    (`smc.run_gm`), within Monte Carlo error (the two runs draw different random numbers).
+"""
+import json
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from conftest import golden
+from oracle import gmfit
+from oracle import smc as osmc
+from oracle.forward import observe, phi as oracle_phi, potential, solve
+from oracle.moves import GM, gm_draw
+from oracle.problem import Problem as OProblem, synthesize
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    d = json.load(open(golden("problem_%s.json" % name)))
+    return d, OProblem(d)
+
+
+def t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def oracle_G(op, xi, n):
+    return np.array([observe(op, solve(op, synthesize(op, x, n), n), n) for x in xi])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2503_16028_amd import smc
+    smc.lib()
+    assert torch.cuda.is_available()
+
+
+def cloud(op, N, seed, M=6, dup=0, sep=3.0):
+    """Prior-like rows whose active coordinates form M clusters (the last `dup` rows repeat row 0)."""
+    xi = inputs.particles(N, op.K, seed)
+    X, *_ = inputs.clusters(N, op.kr, M, seed + 1, sep=sep, dup=dup)
+    xi[:, op.active()] = X
+    if dup:
+        xi[N - dup:] = xi[0]
+    return xi
+
+
+def gpu_fit(p, op, xi, M, iters, seed, ctr, var_floor=1e-3):
+    from paper_2503_16028_amd import smc
+    N = xi.shape[0]
+    logw = torch.empty(M, dtype=torch.float64, device=DEV)
+    mean = torch.empty(M, op.kr, dtype=torch.float64, device=DEV)
+    scale = torch.empty(M, op.kr, dtype=torch.float64, device=DEV)
+    centers = torch.empty(M, dtype=torch.int32, device=DEV)
+    smc.smc_gm_fit(p, N, t(xi), M, iters, var_floor, seed, ctr, logw, mean, scale, centers)
+    torch.cuda.synchronize()
+    return centers.cpu().numpy(), logw.cpu().numpy(), mean.cpu().numpy(), scale.cpu().numpy()
+
+
+FIT_CASES = [
+    ("c3", 4096, 8, 50, 1, 0),      # the 128^2 workload's cloud size and mixture, full EM
+    ("c2", 1000, 8, 20, 2, 0),
+    ("t2", 77, 16, 30, 3, 0),       # ragged N, kr = 12, the largest M
+    ("t1", 5, 3, 10, 4, 0),         # 1D, kr = 8, N barely above M
+    ("c2", 300, 1, 5, 5, 0),        # one component
+    ("c2", 129, 4, 0, 6, 0),        # no EM step: the start itself
+    ("t2", 64, 6, 8, 7, 60),        # 4 distinct rows, 6 centres: Q = 0 forces uniform picks
+]
+
+
+@pytest.mark.parametrize("name,N,M,iters,seed,dup", FIT_CASES)
+def test_gm_fit_against_oracle(name, N, M, iters, seed, dup):
+    from paper_2503_16028_amd import smc
+    banner("gm fit", name, N, M, iters, seed, dup)
+    d, op = load(name)
+    p = smc.Problem(d, N)
+    xi = cloud(op, N, seed, dup=dup)
+    ctr = 77 + seed
+    c, logw, mean, var = gpu_fit(p, op, xi, M, iters, 5 + seed, ctr)
+    X = xi[:, op.active()]
+    rc = gmfit.kmeanspp_philox(X, M, 5 + seed, ctr)
+    assert c.tolist() == rc
+    rlogw, rmean, rvar = gmfit.em(X, *gmfit.start(X, rc), iters)
+    assert np.abs(logw - rlogw).max() <= 1e-9 * max(1.0, np.abs(rlogw).max())
+    assert np.abs(mean - rmean).max() <= 1e-9 * max(1.0, np.abs(rmean).max())
+    assert np.abs(var / rvar - 1).max() <= 1e-9
+    assert abs(np.exp(logw).sum() - 1) < 1e-12 and np.all(var >= 1e-3)
+    assert smc.smc_status_flags(p) == 0
+
+
+def test_gm_fit_repeat_and_smaller():
+    """Two fits in a row on one problem (the EM counter is reset by each launch), the second smaller."""
+    from paper_2503_16028_amd import smc
+    banner("gm fit twice")
+    d, op = load("c2")
+    p = smc.Problem(d, 2000)
+    for N, M, seed in ((2000, 8, 11), (333, 5, 12)):
+        xi = cloud(op, N, seed)
+        c, logw, mean, var = gpu_fit(p, op, xi, M, 15, seed, 3)
+        X = xi[:, op.active()]
+        rc = gmfit.kmeanspp_philox(X, M, seed, 3)
+        assert c.tolist() == rc
+        rlogw, rmean, rvar = gmfit.em(X, *gmfit.start(X, rc), 15)
+        assert np.abs(mean - rmean).max() <= 1e-9 * max(1.0, np.abs(rmean).max())
+        assert np.abs(var / rvar - 1).max() <= 1e-9
+
+
+def test_gm_fit_rejects_bad_arguments():
+    from paper_2503_16028_amd import smc
+    banner("gm fit arguments")
+    d, op = load("t2")
+    p = smc.Problem(d, 10)
+    xi = t(cloud(op, 12, 1))            # room for N = 11, which the library must reject (n_max = 10)
+    lw, mn, sc = (torch.empty(17 * op.kr, dtype=torch.float64, device=DEV) for _ in range(3))
+    bad = [dict(N=0), dict(N=11), dict(M=0), dict(M=17), dict(iters=-1), dict(var_floor=0.0),
+           dict(var_floor=float("nan"))]
+    for b in bad:
+        a = dict(N=10, M=3, iters=2, var_floor=1e-3)
+        a.update(b)
+        with pytest.raises(smc.SMCError):
+            smc.smc_gm_fit(p, a["N"], xi, a["M"], a["iters"], a["var_floor"], 1, 2, lw, mn, sc)
+
+
+# ------------------------------------------------------------------ mixture draw
+
+def _draw_case(name, grid, N, M, prec, seed, level=None, grids=None):
+    from paper_2503_16028_amd import smc
+    d, op = load(name)
+    tol = dict(tol64=1e-13, max_iter=60 * grid, max_sweeps=6) if prec == 0 else dict(tol64=1e-10)
+    p = smc.Problem(d, N, grids=grids or [grid], **tol)
+    logw, mean, scale = inputs.mixture(M, op.kr, seed + 1, spread=0.5)
+    gm = GM(logw, mean, scale, op.active(), op.K)
+    xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    iters = torch.empty(N, dtype=torch.int32, device=DEV)
+    lv = None if level is None else t(level, torch.int32)
+    smc.smc_gm_draw(p, N, (t(logw), t(mean), t(scale)), seed, 500 + seed, lv, prec, xi, phi, iters)
+    torch.cuda.synchronize()
+    rv = gm_draw(gm, seed, 500 + seed, np.arange(N))
+    return p, op, xi.cpu().numpy(), phi.cpu().numpy(), iters.cpu().numpy(), rv
+
+
+@pytest.mark.parametrize("name,grid,N,M", [("c2", 64, 6, 4), ("t2", 32, 16, 3), ("t1", 64, 9, 2)])
+def test_gm_draw_fp64(name, grid, N, M):
+    from paper_2503_16028_amd import smc
+    banner("gm draw fp64", name, grid, N, M)
+    p, op, xi, phi, iters, rv = _draw_case(name, grid, N, M, smc.SMC_FP64, 21)
+    assert np.abs(xi - rv).max() <= 1e-12 * np.abs(rv).max()
+    rphi = potential(oracle_G(op, rv, grid), op.y, op.sigma)
+    assert np.abs(phi / rphi - 1).max() <= 1e-9
+    assert np.all(iters >= 0)                 # converged (the 1D map is a closed form: 0 iterations)
+    assert smc.smc_status_flags(p) == 0
+
+
+def test_gm_draw_fp32_refine_full_size():
+    """The 128^2 workload: 4096 draws in one call; every draw checked, potentials sampled."""
+    from paper_2503_16028_amd import smc
+    banner("gm draw fp32+refine 128^2 N=4096")
+    p, op, xi, phi, iters, rv = _draw_case("c3", 128, 4096, 8, smc.SMC_FP32_REFINE, 22)
+    assert np.abs(xi - rv).max() <= 1e-12 * np.abs(rv).max()
+    assert np.all(np.isfinite(phi)) and np.all(iters > 0)
+    pick = np.random.default_rng(0).choice(4096, 5, replace=False)
+    rphi = potential(oracle_G(op, rv[pick], 128), op.y, op.sigma)
+    assert np.abs(phi[pick] / rphi - 1).max() <= 1e-4
+
+
+def test_gm_draw_level_map():
+    from paper_2503_16028_amd import smc
+    banner("gm draw level map 64/128/256")
+    level = np.array([0, 1, 2, 1, 0, 2, 0], dtype=np.int32)
+    p, op, xi, phi, iters, rv = _draw_case("c5", 64, 7, 4, smc.SMC_FP32_REFINE, 23, level=level,
+                                           grids=[64, 128, 256])
+    assert np.abs(xi - rv).max() <= 1e-12 * np.abs(rv).max()
+    for k, l in enumerate(level):
+        n = [64, 128, 256][l]
+        rphi = potential(oracle_G(op, rv[k:k + 1], n), op.y, op.sigma)[0]
+        assert phi[k] == pytest.approx(rphi, rel=1e-4)
+
+
+def test_gm_draw_rejects_bad_mixture():
+    from paper_2503_16028_amd import smc
+    banner("gm draw arguments")
+    d, op = load("t2")
+    p = smc.Problem(d, 4)
+    xi = torch.empty(5, op.K, dtype=torch.float64, device=DEV)    # room for N = 5 > n_max
+    phi = torch.empty(5, dtype=torch.float64, device=DEV)
+    wrong_kr = (t([0.0]), t(np.zeros((1, op.kr + 1))), t(np.ones((1, op.kr + 1))))
+    with pytest.raises(smc.SMCError):
+        smc.smc_gm_draw(p, 4, wrong_kr, 1, 1, None, smc.SMC_FP64, xi, phi)
+    ok = (t([0.0]), t(np.zeros((1, op.kr))), t(np.ones((1, op.kr))))
+    with pytest.raises(smc.SMCError):
+        smc.smc_gm_draw(p, 5, ok, 1, 1, None, smc.SMC_FP64, xi, phi)
+
+
+# ------------------------------------------------------------------ the SMC-GM loop
+
+def mirrored_1d():
+    """K = 2 sine modes on 16 intervals, observations at 4, 6 and their mirrors 12, 10 with
+    pair-averaged data, so Phi(xi_1, xi_2) = Phi(xi_1, -xi_2): a two-mode posterior."""
+    obs = [4, 6, 12, 10]
+    d = dict(name="mirrored1d", dim=1, grids=[16], kl_per_axis=2, kr=2, obs_den=16, obs=[[o] for o in obs],
+             y=[0.0] * 4, sigma=1.0, f=1.0)
+    p = OProblem(d)
+    G = observe(p, solve(p, synthesize(p, np.array([0.8, 1.6]), 64), 64), 64)
+    sigma = 0.05 * np.abs(G).max()
+    noise = sigma * np.random.default_rng(2).standard_normal(2)
+    y = np.concatenate([0.5 * (G[:2] + G[2:]) + noise] * 2)
+    d["y"], d["sigma"] = [float(v) for v in y], float(sigma)
+    return d, OProblem(d)
+
+
+def test_smc_gm_run_against_oracle_run():
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCGMSampler
+    banner("smc-gm run 1d bimodal")
+    d, op = mirrored_1d()
+    No, Ng = 2000, 4096
+    ref = osmc.run_gm(op, 16, No, M=2, rho=0.5, seed=3, phi_fn=lambda x: oracle_phi(op, x, 16), kr=2, iters=50)
+    p = smc.Problem(d, Ng, tol64=1e-13)
+    out = SMCGMSampler(p, Ng, M=2, ess_frac=0.5, prec=smc.SMC_FP64, seed=4).run()
+    xg, xo = out["xi"].cpu().numpy(), ref["xi"]
+    assert out["history"][-1]["tau"] == 1.0 and ref["taus"][-1] == 1.0
+    se = lambda a, n: a.std() * math.sqrt(4.0 / n)           # effective size N / 4 (resampling, refits)
+    for k in range(2):
+        assert abs(xg[:, k].mean() - xo[:, k].mean()) < 4 * math.hypot(se(xg[:, k], Ng), se(xo[:, k], No))
+        assert abs(xg[:, k].std() / xo[:, k].std() - 1) < 4 * math.sqrt(2 * (4.0 / Ng + 4.0 / No))
+    m_g, m_o = np.mean(xg[:, 1] > 0), np.mean(xo[:, 1] > 0)
+    assert abs(m_g - m_o) < 4 * math.sqrt(0.25 * (4.0 / Ng + 4.0 / No))
+    assert abs(out["log_Z"] - ref["log_Z"]) < 0.3
+    assert smc.smc_status_flags(p) == 0
