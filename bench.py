@@ -113,6 +113,35 @@ def pcnl_variant(dev, N=2048, n_moves=20):
             "pcnl_cg_iters_per_solve": pr["iters"] / max(1, pr["solves"])}
 
 
+def smc_gm_variant(dev, N=4096, M=8, stages=3):
+    """SMC-GM (Alg. 3) at 128^2: per stage re-weighting, resampling, the device mixture fit (k-means++
+    and 50 EM steps) and N fresh draws with their solves; and the fit alone."""
+    import torch
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCGMSampler, fit_mixture
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_c3.json")))
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-5)
+    s = SMCGMSampler(p, N, M, ess_frac=0.5, prec=smc.SMC_FP32_REFINE, seed=2503, device=dev)
+    s.initialise()
+    s.step()                                        # warm-up stage
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(stages):
+        s.step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / stages
+    reps = 5
+    fit_mixture(p, N, s.xi, M, 1, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        fit_mixture(p, N, s.xi, M, 1, 2 + r)
+    torch.cuda.synchronize()
+    fit_ms = 1e3 * (time.perf_counter() - t0) / reps
+    return {"smc_gm_128_N4096_particles_per_s": N / dt, "smc_gm_stage_ms": 1e3 * dt,
+            "gm_fit_ms_N4096_M8_50em": fit_ms}
+
+
 def mixed_variant(dev, counts=(4096, 3072, 1024), n_moves=20, stages=2):
     """Three samplers on 64^2, 128^2 and 256^2 (N = 8192) moved by one captured stage graph."""
     import numpy as np
@@ -241,6 +270,7 @@ def main():
     variants = {}
     if not args.no_variants:
         variants.update(pcnl_variant(dev))
+        variants.update(smc_gm_variant(dev))
         variants.update(mixed_variant(dev))
         t64, prof64, _ = stage_loop(smc.SMC_FP64, 1, 0, 4)
         variants["fp64_batched_moves_per_s"] = N * 4 / t64

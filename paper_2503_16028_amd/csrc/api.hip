@@ -63,7 +63,7 @@ static void free_problem(Problem& P) {
     f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_lam); f(P.ws_gnew); f(P.ws_sd);
     f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.ws_list); f(P.ws_counters); f(P.flags); f(P.stats);
-    f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers); f(P.ws_fit_counter);
+    f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers);
 }
 
 extern "C" const char* smc_last_error(void) { return g_err.c_str(); }
@@ -222,11 +222,9 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     {
         const size_t pe = (size_t)MAX_M * (1 + 2 * MAX_KR);
         ck(hipMalloc((void**)&P.ws_fit_d2, sizeof(double) * Nm));
-        ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * pe));
+        ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * GM_PAR));
         ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * pe));
         ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
-        ck(hipMalloc((void**)&P.ws_fit_counter, sizeof(unsigned int)));
-        ck(hipMemset(P.ws_fit_counter, 0, sizeof(unsigned int)));
     }
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
@@ -613,7 +611,7 @@ extern "C" int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M,
     if (iters < 0 || iters > 100000) return fail(SMC_E_INVAL, "iters must be 0..100000");
     if (!(var_floor > 0.0) || !std::isfinite(var_floor)) return fail(SMC_E_INVAL, "var_floor must be positive");
     if (!xi || !logw || !mean || !scale) return fail(SMC_E_INVAL, "xi, logw, mean and scale must not be NULL");
-    FitWorkspace w{P.ws_fit_d2, P.ws_fit_par, P.ws_fit_part, P.ws_fit_counter};
+    FitWorkspace w{P.ws_fit_d2, P.ws_fit_par, P.ws_fit_part};
     HIPCHK(launch_gm_fit(N, P.K, P.kr, P.active, xi, M, iters, var_floor, seed, ctr, w,
                          centers ? centers : P.ws_fit_centers, logw, mean, scale, (hipStream_t)stream));
     return SMC_OK;

@@ -11,6 +11,7 @@ constexpr int MAX_LEVELS = 3;
 constexpr int MAX_OBS = 64;
 constexpr int MAX_M = 16;
 constexpr int MAX_KR = 64;
+constexpr int GM_PAR = 2 * MAX_M + 4 * MAX_M * MAX_KR;   // doubles in one mixture-fit parameter block
 constexpr int KLP = 32;          // 2D modes per axis, padded, in the synthesis tiles
 constexpr uint32_t UNIFORM_BLOCK = 0x80000000u;
 
@@ -50,10 +51,9 @@ struct Problem {
     int32_t* ws_list = nullptr;  // [n_max] work list of a level map (particles grouped by grid)
     unsigned long long* ws_counters = nullptr;   // [2] work and exit counters of the persistent solve
     double* ws_fit_d2 = nullptr;      // [n_max]   squared distance to the nearest seeded centre
-    double* ws_fit_par = nullptr;     // [2][MAX_M][1 + 2 MAX_KR]  EM parameters (ping-pong)
-    double* ws_fit_part = nullptr;    // [em blocks][MAX_M][1 + 2 MAX_KR]  EM partial sums
+    double* ws_fit_par = nullptr;     // [2][GM_PAR]  EM parameter blocks (ping-pong)
+    double* ws_fit_part = nullptr;    // [workgroups of 128 particles][MAX_M][1 + 2 MAX_KR]  partial sums
     int32_t* ws_fit_centers = nullptr;  // [MAX_M] seeded rows
-    unsigned int* ws_fit_counter = nullptr;   // workgroups done in the current EM launch
     int n_cu = 0;                // compute units of the device
     int32_t* flags = nullptr;    // device status word
     unsigned long long* stats = nullptr;  // [4] iterations, sweeps, solves, preconditioner applications
@@ -246,7 +246,6 @@ struct FitWorkspace {
     double* d2;
     double* par;
     double* part;
-    unsigned int* counter;
 };
 int64_t em_blocks(int64_t N);
 hipError_t prepare_gmfit_kernels();

@@ -14,9 +14,14 @@
 //
 // EM: E-step R_nj = w_j N(x_n; m_j, s_j) / sum_i w_i N(x_n; m_i, s_i) in log space; M-step
 // N_j = sum_n R_nj (+1e-300), w_j = N_j / N, m_j = sum_n R_nj x_n / N_j,
-// s_j = max(sum_n R_nj x_n^2 / N_j - m_j^2, floor).  One launch per iteration: each workgroup
-// reduces 128 particles to partial sums; the last workgroup to finish adds the partials in a fixed
-// order (so the result does not depend on scheduling) and writes the next parameters.
+// s_j = max(sum_n R_nj x_n^2 / N_j - m_j^2, floor).
+//
+// Layout of the work: every pass over the cloud runs on workgroups of 64 particles whose active
+// coordinates are first staged, transposed, in LDS (lanes read one row's coordinates together).
+// Reductions over the cloud leave one partial per workgroup in global memory and a one-workgroup
+// kernel adds them in workgroup order, so results never depend on scheduling.  Passing partials
+// between kernels, rather than through a last-workgroup handshake inside one kernel, avoids a
+// device-scope fence per workgroup (an L2 write-back on this part) in every iteration.
 #include "common.hpp"
 
 namespace smc {
@@ -25,8 +30,15 @@ namespace {
 
 constexpr uint32_t KMPP_BLOCK = 0x80000002u;
 constexpr int QBITS = 40;
-constexpr int EM_P = 128;            // particles per EM workgroup
+constexpr int EM_P = 64;             // particles per workgroup
 constexpr int EM_LDX = EM_P + 1;     // padded row of the transposed particle slice
+
+// Parameter block (GM_PAR doubles, two of them ping-pong between iterations):
+//   logw [MAX_M], cst [MAX_M] (log w_j - sum_d log(2 pi s_jd) / 2), mean [MAX_M][MAX_KR],
+//   var [MAX_M][MAX_KR], and for the E-step, coordinate-major: meanT [MAX_KR][MAX_M], ivT (1 / var).
+constexpr int PAR_LOGW = 0, PAR_CST = MAX_M, PAR_MEAN = 2 * MAX_M, PAR_VAR = PAR_MEAN + MAX_M * MAX_KR,
+              PAR_MEANT = PAR_VAR + MAX_M * MAX_KR, PAR_IVT = PAR_MEANT + MAX_KR * MAX_M;
+static_assert(PAR_IVT + MAX_KR * MAX_M == GM_PAR, "parameter block layout");
 
 __device__ __forceinline__ uint64_t kmpp_u53(uint64_t seed, uint64_t ctr, int m) {
     const uint4 w = draw(seed, ctr, KMPP_BLOCK, (uint32_t)m);
@@ -42,38 +54,103 @@ __device__ __forceinline__ uint64_t qweight(double d2, int shift) {
     return (d2 > 0.0 && d2 < INFINITY) ? (uint64_t)floor(ldexp(d2, shift)) : 0ull;
 }
 
+// The workgroup's particles [n0, n0 + np) staged transposed: xs[d * EM_LDX + p] = x_{n0+p, d}
+// (zero beyond np).  Four waves; the 16 loads of a lane go out before the first store (rows
+// clamped into range, zeros selected afterwards).
+__device__ __forceinline__ void stage_rows(double* xs, const double* __restrict__ xi, const int32_t* __restrict__ active,
+                                           int K, int kr, int64_t n0, int np) {
+    constexpr int PER = EM_P / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = active[lane < kr ? lane : 0];
+    double v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int p = wave + 4 * i;
+        v[i] = xi[(n0 + (p < np ? p : np - 1)) * K + k];
+    }
+    if (lane < kr) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int p = wave + 4 * i;
+            xs[lane * EM_LDX + p] = p < np ? v[i] : 0.0;
+        }
+    }
+}
+
+// Sum of a[b * stride + e] over b = 0 .. B-1, added in that order; the loads go out 32 at a time.
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ a, int B, int64_t stride, int e) {
+    double s = 0.0;
+    for (int b0 = 0; b0 < B; b0 += 32) {
+        double v[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int b = b0 + k < B ? b0 + k : B - 1;
+            v[k] = a[(int64_t)b * stride + e];
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) s += b0 + k < B ? v[k] : 0.0;
+    }
+    return s;
+}
+
+// Publish parameters held in LDS (lw[M], mu[M][MAX_KR], va[M][MAX_KR]) into a parameter block
+// (the LDS arrays must be complete: callers put a barrier before).
+__device__ __forceinline__ void publish(double* __restrict__ par, int M, int kr, const double* lw, const double* mu,
+                                        const double* va) {
+    for (int i = threadIdx.x; i < M * kr; i += blockDim.x) {
+        const int j = i / kr, d = i % kr;
+        const double m = mu[j * MAX_KR + d], v = va[j * MAX_KR + d];
+        par[PAR_MEAN + j * MAX_KR + d] = m;
+        par[PAR_VAR + j * MAX_KR + d] = v;
+        par[PAR_MEANT + d * MAX_M + j] = m;
+        par[PAR_IVT + d * MAX_M + j] = 1.0 / v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wave; j < M; j += nw) {   // one wave per component, lanes are coordinates
+        const double s = wave_sum(lane < kr ? log(2.0 * M_PI * va[j * MAX_KR + lane]) : 0.0);
+        if (lane == 0) {
+            par[PAR_LOGW + j] = lw[j];
+            par[PAR_CST + j] = lw[j] - 0.5 * s;
+        }
+    }
+}
+
 }  // namespace
 
-// d2_n <- min(d2_n, |x_n - x_c|^2) for the last chosen centre c (d2_n <- |x_n - x_c|^2 when m = 1).
+// ------------------------------------------------------------------ seeding
+
+// d2_n <- min(d2_n, |x_n - x_c|^2) for the last chosen centre c (d2_n <- |x_n - x_c|^2 when m = 1);
+// 64 particles per workgroup, one thread per particle after staging.
 __global__ __launch_bounds__(256) void kmpp_dist_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
                                                         const double* __restrict__ xi,
                                                         const int32_t* __restrict__ centers, int m,
                                                         double* __restrict__ d2) {
 #pragma clang fp contract(off)
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
-    const double* x = xi + n * K;
-    const double* c = xi + (int64_t)centers[m - 1] * K;
+    __shared__ double xs[MAX_KR * EM_LDX];
+    __shared__ double cs[64];
+    const int64_t n0 = (int64_t)blockIdx.x * EM_P;
+    const int np = (int)(N - n0 < EM_P ? N - n0 : EM_P);
+    stage_rows(xs, xi, active, K, kr, n0, np);
+    if (threadIdx.x < 64) {
+        const int d = threadIdx.x;
+        cs[d] = d < kr ? xi[(int64_t)centers[m - 1] * K + active[d]] : 0.0;
+    }
+    __syncthreads();
+    const int p = threadIdx.x;
+    if (p >= np) return;
     double s[32];
 #pragma unroll
     for (int d = 0; d < 32; ++d) {
-        double a = 0.0, b = 0.0;
-        if (d < kr) {
-            const int k = active[d];
-            const double t = x[k] - c[k];
-            a = t * t;
-        }
-        if (d + 32 < kr) {
-            const int k = active[d + 32];
-            const double t = x[k] - c[k];
-            b = t * t;
-        }
+        const double ta = xs[(d < kr ? d : 0) * EM_LDX + p] - cs[d];
+        const double tb = xs[(d + 32 < kr ? d + 32 : 0) * EM_LDX + p] - cs[d + 32];
+        const double a = d < kr ? ta * ta : 0.0, b = d + 32 < kr ? tb * tb : 0.0;
         s[d] = a + b;
     }
 #pragma unroll
     for (int w = 16; w >= 1; w >>= 1)
 #pragma unroll
         for (int d = 0; d < w; ++d) s[d] = s[d] + s[d + w];
+    const int64_t n = n0 + p;
     d2[n] = (m == 1) ? s[0] : fmin(d2[n], s[0]);
 }
 
@@ -137,140 +214,149 @@ __global__ __launch_bounds__(1024) void kmpp_pick_kernel(int64_t N, int m, uint6
     }
 }
 
-// EM start: w_j = 1/M, m_j = the seeded rows, s_j = max(population variance of the cloud, floor).
-// par[j] = {log w_j, m_j[0..kr), s_j[0..kr)}.  One workgroup of 1024 threads; lanes are coordinates.
-__global__ __launch_bounds__(1024) void gm_start_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
-                                                        const double* __restrict__ xi,
-                                                        const int32_t* __restrict__ centers, int M,
-                                                        double var_floor, double* __restrict__ par) {
-    __shared__ double red[16][64];
-    __shared__ double mu[64];
+// ------------------------------------------------------------------ EM start
+
+// Column sums of x - c and (x - c)^2 per workgroup (c = the first seeded row, a shift that keeps
+// the one-pass variance accurate): part[b][0..kr) and part[b][kr..2kr).
+__global__ __launch_bounds__(256) void gm_colstats_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
+                                                          const double* __restrict__ xi,
+                                                          const int32_t* __restrict__ centers,
+                                                          double* __restrict__ part) {
+    __shared__ double xs[MAX_KR * EM_LDX];
+    __shared__ double red[4][2][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k = lane < kr ? active[lane] : 0;
-    double acc = 0.0;
-    if (lane < kr)
-        for (int64_t n = wave; n < N; n += 16) acc += xi[n * K + k];
-    red[wave][lane] = acc;
+    const int64_t n0 = (int64_t)blockIdx.x * EM_P;
+    const int np = (int)(N - n0 < EM_P ? N - n0 : EM_P);
+    stage_rows(xs, xi, active, K, kr, n0, np);
     __syncthreads();
-    if (tid < 64) {
-        double s = 0.0;
-        for (int w = 0; w < 16; ++w) s += red[w][tid];
-        mu[tid] = s / (double)N;
-    }
-    __syncthreads();
-    const double mean = mu[lane];
-    acc = 0.0;
-    if (lane < kr)
-        for (int64_t n = wave; n < N; n += 16) {
-            const double t = xi[n * K + k] - mean;
-            acc += t * t;
-        }
-    __syncthreads();
-    red[wave][lane] = acc;
-    __syncthreads();
-    const int E = 1 + 2 * kr;
-    if (tid < kr) {
-        double s = 0.0;
-        for (int w = 0; w < 16; ++w) s += red[w][tid];
-        const double v = fmax(s / (double)N, var_floor);
-        for (int j = 0; j < M; ++j) {
-            par[j * E + 1 + tid] = xi[(int64_t)centers[j] * K + active[tid]];
-            par[j * E + 1 + kr + tid] = v;
+    double s1 = 0.0, s2 = 0.0;
+    if (lane < kr) {
+        const double c = xi[(int64_t)centers[0] * K + active[lane]];
+        for (int p = 16 * wave; p < 16 * wave + 16 && p < np; ++p) {
+            const double t = xs[lane * EM_LDX + p] - c;
+            s1 += t;
+            s2 += t * t;
         }
     }
-    if (tid < M) par[tid * E] = -log((double)M);
+    red[wave][0][lane] = s1;
+    red[wave][1][lane] = s2;
+    __syncthreads();
+    if (tid < 2 * kr) {
+        const int q = tid / kr, d = tid % kr;
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += red[w][q][d];
+        part[(int64_t)blockIdx.x * 2 * kr + tid] = s;
+    }
 }
 
-// One EM iteration (see the file comment).  par_in -> par_out, or -> the outputs when `last`.
-__global__ __launch_bounds__(256) void em_iter_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
-                                                      const double* __restrict__ xi, int M, double var_floor,
-                                                      const double* __restrict__ par_in, double* part,
-                                                      unsigned int* counter, int last, double* __restrict__ par_out,
-                                                      double* __restrict__ out_logw, double* __restrict__ out_mean,
-                                                      double* __restrict__ out_scale) {
+// EM start: w_j = 1/M, m_j = the seeded rows, s_j = max(population variance of the cloud, floor).
+__global__ __launch_bounds__(256) void gm_start_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
+                                                       const double* __restrict__ xi,
+                                                       const int32_t* __restrict__ centers, int M,
+                                                       double var_floor, int B, const double* __restrict__ part,
+                                                       double* __restrict__ par) {
+    __shared__ double lw[MAX_M], mu[MAX_M * MAX_KR], va[MAX_M * MAX_KR], col[2 * MAX_KR];
+    const int tid = threadIdx.x;
+    if (tid < 2 * kr) col[(tid / kr) * MAX_KR + tid % kr] = ordered_sum(part, B, 2 * kr, tid);
+    __syncthreads();
+    for (int i = tid; i < M * kr; i += 256) {
+        const int j = i / kr, d = i % kr;
+        const double m1 = col[d] / (double)N;
+        mu[j * MAX_KR + d] = xi[(int64_t)centers[j] * K + active[d]];
+        va[j * MAX_KR + d] = fmax(col[MAX_KR + d] / (double)N - m1 * m1, var_floor);
+    }
+    if (tid < M) lw[tid] = -log((double)M);
+    __syncthreads();
+    publish(par, M, kr, lw, mu, va);
+}
+
+// ------------------------------------------------------------------ EM iterations
+
+// E-step and the M-step's partial sums of one workgroup: part[b][j] = {sum R, sum R x, sum R x^2}
+// over its 64 particles (E = 1 + 2 kr entries per component).  MB >= M components are computed
+// without branches; those beyond M are masked out of the responsibilities and never written.
+template <int MB>
+__global__ __launch_bounds__(256) void em_partial_kernel(int64_t N, int K, int kr, const int32_t* __restrict__ active,
+                                                         const double* __restrict__ xi, int M,
+                                                         const double* __restrict__ par,
+                                                         double* __restrict__ part) {
     extern __shared__ double smem[];
     double* xs = smem;                         // [kr][EM_LDX]  the workgroup's particles, transposed
-    double* ms = xs + MAX_KR * EM_LDX;         // [M][kr]       means
-    double* is = ms + MAX_M * MAX_KR;          // [M][kr]       1 / variances
-    double* cs = is + MAX_M * MAX_KR;          // [M]           log w_j - sum_d log(2 pi s_jd) / 2
-    double* sp = cs + MAX_M;                   // [2][EM_P][M]  half sums of the E-step, then R
-    __shared__ int is_last;
+    double* sp = xs + MAX_KR * EM_LDX;         // [4][EM_P][MAX_M]  quarter sums of the E-step, then R
+    double* pm = sp + 4 * EM_P * MAX_M;        // [kr][MB]  means, coordinate-major
+    double* pv = pm + MAX_KR * MB;             // [kr][MB]  1 / variances
+    double* pc = pv + MAX_KR * MB;             // [MB]      log w_j - sum_d log(2 pi s_jd) / 2
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int E = 1 + 2 * kr;
     const int64_t n0 = (int64_t)blockIdx.x * EM_P;
     const int np = (int)(N - n0 < EM_P ? N - n0 : EM_P);
-
-    for (int i = tid; i < M * kr; i += 256) {
-        const int j = i / kr, d = i % kr;
-        ms[j * MAX_KR + d] = par_in[j * E + 1 + d];
-        is[j * MAX_KR + d] = 1.0 / par_in[j * E + 1 + kr + d];
+    for (int i = tid; i < kr * MB; i += 256) {   // the parameters go out with the rows' loads
+        pm[i] = par[PAR_MEANT + (i / MB) * MAX_M + i % MB];
+        pv[i] = par[PAR_IVT + (i / MB) * MAX_M + i % MB];
     }
-    if (tid < M) {
-        double s = 0.0;
-        for (int d = 0; d < kr; ++d) s += log(2.0 * M_PI * par_in[tid * E + 1 + kr + d]);
-        cs[tid] = par_in[tid * E] - 0.5 * s;
-    }
-    if (lane < kr) {
-        const int k = active[lane];
-        for (int p = wave; p < EM_P; p += 4) xs[lane * EM_LDX + p] = p < np ? xi[(n0 + p) * K + k] : 0.0;
-    }
+    if (tid < MB) pc[tid] = par[PAR_CST + tid];
+    stage_rows(xs, xi, active, K, kr, n0, np);
     __syncthreads();
 
-    {   // E-step, half the coordinates per thread
-        const int p = tid & (EM_P - 1), h = tid >> 7;
-        const int dlo = h ? kr / 2 : 0, dhi = h ? kr : kr / 2;
-        for (int j = 0; j < M; ++j) {
-            double s = 0.0;
-            for (int d = dlo; d < dhi; ++d) {
-                const double t = xs[d * EM_LDX + p] - ms[j * MAX_KR + d];
-                s += t * t * is[j * MAX_KR + d];
+    {   // E-step, a quarter of the coordinates per thread (wave); parameters are LDS broadcasts
+        const int p = tid & (EM_P - 1), h = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int dlo = h * kr / 4, dhi = (h + 1) * kr / 4;
+        double s[MB];
+#pragma unroll
+        for (int j = 0; j < MB; ++j) s[j] = 0.0;
+#pragma unroll 4
+        for (int d = dlo; d < dhi; ++d) {
+            const double x = xs[d * EM_LDX + p];
+#pragma unroll
+            for (int j = 0; j < MB; ++j) {
+                const double t = x - pm[d * MB + j];
+                s[j] += t * t * pv[d * MB + j];
             }
-            sp[(h * EM_P + p) * MAX_M + j] = s;
         }
+#pragma unroll
+        for (int j = 0; j < MB; ++j) sp[(h * EM_P + p) * MAX_M + j] = s[j];
     }
     __syncthreads();
     if (tid < EM_P) {
         const int p = tid;
-        double ll[MAX_M];
+        double ll[MB];
         double mx = -INFINITY;
 #pragma unroll
-        for (int j = 0; j < MAX_M; ++j) {
-            if (j < M) {
-                ll[j] = cs[j] - 0.5 * (sp[p * MAX_M + j] + sp[(EM_P + p) * MAX_M + j]);
-                mx = fmax(mx, ll[j]);
-            }
+        for (int j = 0; j < MB; ++j) {
+            const double q = ((sp[p * MAX_M + j] + sp[(EM_P + p) * MAX_M + j]) + sp[(2 * EM_P + p) * MAX_M + j]) +
+                             sp[(3 * EM_P + p) * MAX_M + j];
+            const double v = pc[j] - 0.5 * q;
+            ll[j] = j < M ? v : -INFINITY;
+            mx = fmax(mx, ll[j]);
         }
         double se = 0.0;
 #pragma unroll
-        for (int j = 0; j < MAX_M; ++j)
-            if (j < M) se += exp(ll[j] - mx);
+        for (int j = 0; j < MB; ++j) se += j < M ? exp(ll[j] - mx) : 0.0;
         const double lse = mx + log(se);
 #pragma unroll
-        for (int j = 0; j < MAX_M; ++j)
-            if (j < M) sp[p * MAX_M + j] = p < np ? exp(ll[j] - lse) : 0.0;
+        for (int j = 0; j < MB; ++j) sp[p * MAX_M + j] = (p < np && j < M) ? exp(ll[j] - lse) : 0.0;
     }
     __syncthreads();
 
-    // M-step partial sums: wave w takes particles [32 w, 32 w + 32); lanes are coordinates
-    double a1[MAX_M], a2[MAX_M], a0 = 0.0;
+    // M-step partial sums: wave w takes particles [16 w, 16 w + 16); lanes are coordinates
+    double a1[MB], a2[MB], a0 = 0.0;
 #pragma unroll
-    for (int j = 0; j < MAX_M; ++j) a1[j] = a2[j] = 0.0;
-    for (int p = 32 * wave; p < 32 * wave + 32; ++p) {
+    for (int j = 0; j < MB; ++j) a1[j] = a2[j] = 0.0;
+#pragma unroll 4
+    for (int p = 16 * wave; p < 16 * wave + 16; ++p) {
         const double x = lane < kr ? xs[lane * EM_LDX + p] : 0.0, xx = x * x;
 #pragma unroll
-        for (int j = 0; j < MAX_M; ++j) {
-            if (j < M) {
-                const double r = sp[p * MAX_M + j];
-                a1[j] += r * x;
-                a2[j] += r * xx;
-            }
+        for (int j = 0; j < MB; ++j) {
+            const double r = sp[p * MAX_M + j];
+            a1[j] += r * x;
+            a2[j] += r * xx;
         }
         if (lane < M) a0 += sp[p * MAX_M + lane];
     }
-    __syncthreads();                       // xs is reused for the per-wave partials below
-    double* wpart = xs;                    // [4][M][E]
+    __syncthreads();                       // xs and sp are reused for the per-wave partials below
+    double* wpart = smem;                  // [4][MAX_M][E]
 #pragma unroll
-    for (int j = 0; j < MAX_M; ++j) {
+    for (int j = 0; j < MB; ++j) {
         if (j < M && lane < kr) {
             wpart[(wave * MAX_M + j) * E + 1 + lane] = a1[j];
             wpart[(wave * MAX_M + j) * E + 1 + kr + lane] = a2[j];
@@ -285,73 +371,61 @@ __global__ __launch_bounds__(256) void em_iter_kernel(int64_t N, int K, int kr, 
         for (int w = 0; w < 4; ++w) s += wpart[(w * MAX_M + j) * E + e];
         bpart[j * E + e] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!__builtin_amdgcn_readfirstlane(is_last)) return;
+}
 
-    // the last workgroup: add the partials in workgroup order, then the M-step
-    __threadfence();
-    double* tot = smem;                    // [M][E]
-    const int B = gridDim.x;
-    for (int i = tid; i < M * E; i += 256) {
-        const int j = i / E, e = i % E;
-        double s = 0.0;
-        for (int b = 0; b < B; ++b) s += part[((int64_t)b * MAX_M + j) * E + e];
-        tot[j * E + e] = s;
-    }
+// M-step of component j = blockIdx.x: its partials from B workgroups added in workgroup order,
+// then its entries of the next parameter block.  One workgroup per component.
+__global__ __launch_bounds__(256) void em_final_kernel(int64_t N, int kr, double var_floor, int B,
+                                                       const double* __restrict__ part, double* __restrict__ par) {
+    __shared__ double tot[1 + 2 * MAX_KR];
+    const int tid = threadIdx.x, lane = tid & 63, j = blockIdx.x;
+    const int E = 1 + 2 * kr;
+    if (tid < E) tot[tid] = ordered_sum(part + (int64_t)j * E, B, (int64_t)MAX_M * E, tid);
     __syncthreads();
-    double* lw = tot + MAX_M * E;          // [M]
-    if (tid < M) {
-        const double nk = tot[tid * E] + 1e-300;
-        lw[tid] = log(nk / (double)N);
-    }
-    __syncthreads();
-    double lse = 0.0;
-    if (last) {
-        double mx = -INFINITY;
-        for (int j = 0; j < M; ++j) mx = fmax(mx, lw[j]);
-        double s = 0.0;
-        for (int j = 0; j < M; ++j) s += exp(lw[j] - mx);
-        lse = mx + log(s);
-    }
-    for (int i = tid; i < M * kr; i += 256) {
-        const int j = i / kr, d = i % kr;
-        const double nk = tot[j * E] + 1e-300;
-        const double m = tot[j * E + 1 + d] / nk;
-        const double v = fmax(tot[j * E + 1 + kr + d] / nk - m * m, var_floor);
-        if (last) {
-            out_mean[j * kr + d] = m;
-            out_scale[j * kr + d] = v;
-        } else {
-            par_out[j * E + 1 + d] = m;
-            par_out[j * E + 1 + kr + d] = v;
+    const double nk = tot[0] + 1e-300;
+    const double lw = log(nk / (double)N);
+    if (tid < 64) {   // wave 0: lanes are coordinates
+        const int d = lane;
+        double lg = 0.0;
+        if (d < kr) {
+            const double m = tot[1 + d] / nk;
+            const double v = fmax(tot[1 + kr + d] / nk - m * m, var_floor);
+            par[PAR_MEAN + j * MAX_KR + d] = m;
+            par[PAR_VAR + j * MAX_KR + d] = v;
+            par[PAR_MEANT + d * MAX_M + j] = m;
+            par[PAR_IVT + d * MAX_M + j] = 1.0 / v;
+            lg = log(2.0 * M_PI * v);
+        }
+        const double s = wave_sum(lg);
+        if (lane == 0) {
+            par[PAR_LOGW + j] = lw;
+            par[PAR_CST + j] = lw - 0.5 * s;
         }
     }
-    if (tid < M) {
-        if (last)
-            out_logw[tid] = lw[tid] - lse;
-        else
-            par_out[tid * E] = lw[tid];
-    }
-    if (tid == 0) atomicExch(counter, 0u);   // ready for the next launch (and graph replays)
 }
 
-// No EM steps: the start itself, weights normalised.
-__global__ void gm_copy_start_kernel(int M, int kr, const double* __restrict__ par, double* __restrict__ out_logw,
-                                     double* __restrict__ out_mean, double* __restrict__ out_scale) {
-    const int E = 1 + 2 * kr;
+// The fit's outputs from a parameter block: weights normalised (log w_j - LSE_i log w_i), means and
+// variances.
+__global__ void gm_output_kernel(int M, int kr, const double* __restrict__ par, double* __restrict__ out_logw,
+                                 double* __restrict__ out_mean, double* __restrict__ out_scale) {
     for (int i = threadIdx.x; i < M * kr; i += blockDim.x) {
         const int j = i / kr, d = i % kr;
-        out_mean[j * kr + d] = par[j * E + 1 + d];
-        out_scale[j * kr + d] = par[j * E + 1 + kr + d];
+        out_mean[j * kr + d] = par[PAR_MEAN + j * MAX_KR + d];
+        out_scale[j * kr + d] = par[PAR_VAR + j * MAX_KR + d];
     }
-    if ((int)threadIdx.x < M) out_logw[threadIdx.x] = par[threadIdx.x * E];
+    if ((int)threadIdx.x < M) {
+        double mx = -INFINITY;
+        for (int j = 0; j < M; ++j) mx = fmax(mx, par[PAR_LOGW + j]);
+        double se = 0.0;
+        for (int j = 0; j < M; ++j) se += exp(par[PAR_LOGW + j] - mx);
+        out_logw[threadIdx.x] = par[PAR_LOGW + threadIdx.x] - (mx + log(se));
+    }
 }
 
-size_t em_smem_bytes() {
-    return sizeof(double) * (MAX_KR * EM_LDX + 2 * MAX_M * MAX_KR + MAX_M + 2 * EM_P * MAX_M);
+static size_t em_smem_bytes() {
+    constexpr size_t work = MAX_KR * EM_LDX + 4 * EM_P * MAX_M + 2 * MAX_KR * MAX_M + MAX_M,
+                     wpart = 4 * MAX_M * (1 + 2 * MAX_KR);
+    return sizeof(double) * (work > wpart ? work : wpart);
 }
 
 int64_t em_blocks(int64_t N) { return (N + EM_P - 1) / EM_P; }
@@ -360,31 +434,37 @@ hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const 
                          double var_floor, uint64_t seed, uint64_t ctr, const FitWorkspace& w, int32_t* centers,
                          double* logw, double* mean, double* scale, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const unsigned gd = (unsigned)((N + 255) / 256);
+    const unsigned B = (unsigned)em_blocks(N);
     kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, 0, seed, ctr, w.d2, centers);
     for (int m = 1; m < M; ++m) {
-        kmpp_dist_kernel<<<gd, 256, 0, s>>>(N, K, kr, active, xi, centers, m, w.d2);
+        kmpp_dist_kernel<<<B, 256, 0, s>>>(N, K, kr, active, xi, centers, m, w.d2);
         kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, m, seed, ctr, w.d2, centers);
     }
-    gm_start_kernel<<<1, 1024, 0, s>>>(N, K, kr, active, xi, centers, M, var_floor, w.par);
-    if (iters == 0) {
-        gm_copy_start_kernel<<<1, 256, 0, s>>>(M, kr, w.par, logw, mean, scale);
-        return hipGetLastError();
-    }
-    const unsigned B = (unsigned)em_blocks(N);
-    const size_t pe = (size_t)MAX_M * (1 + 2 * MAX_KR);
+    gm_colstats_kernel<<<B, 256, 0, s>>>(N, K, kr, active, xi, centers, w.part);
+    gm_start_kernel<<<1, 256, 0, s>>>(N, K, kr, active, xi, centers, M, var_floor, (int)B, w.part, w.par);
+    const size_t lds = em_smem_bytes();
     for (int it = 0; it < iters; ++it) {
-        const double* pin = w.par + (it & 1) * pe;
-        double* pout = w.par + ((it + 1) & 1) * pe;
-        em_iter_kernel<<<B, 256, em_smem_bytes(), s>>>(N, K, kr, active, xi, M, var_floor, pin, w.part, w.counter,
-                                                       it == iters - 1, pout, logw, mean, scale);
+        const double* pin = w.par + (it & 1) * GM_PAR;
+        double* pout = w.par + ((it + 1) & 1) * GM_PAR;
+        if (M <= 4)
+            em_partial_kernel<4><<<B, 256, lds, s>>>(N, K, kr, active, xi, M, pin, w.part);
+        else if (M <= 8)
+            em_partial_kernel<8><<<B, 256, lds, s>>>(N, K, kr, active, xi, M, pin, w.part);
+        else
+            em_partial_kernel<16><<<B, 256, lds, s>>>(N, K, kr, active, xi, M, pin, w.part);
+        em_final_kernel<<<M, 256, 0, s>>>(N, kr, var_floor, (int)B, w.part, pout);
     }
+    gm_output_kernel<<<1, 256, 0, s>>>(M, kr, w.par + (iters & 1) * GM_PAR, logw, mean, scale);
     return hipGetLastError();
 }
 
 hipError_t prepare_gmfit_kernels() {
-    return hipFuncSetAttribute((const void*)em_iter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)em_smem_bytes());
+    const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
+    const int bytes = (int)em_smem_bytes();
+    hipError_t e = hipFuncSetAttribute((const void*)em_partial_kernel<4>, A, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)em_partial_kernel<8>, A, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)em_partial_kernel<16>, A, bytes);
+    return e;
 }
 
 }  // namespace smc
