@@ -18,6 +18,7 @@ Modules
   gmfit      diagonal Gaussian-mixture EM with k-means++ seeding (the stage input)
   smc        the SMC loop of Alg. 1 with the pCN-GM mutation (SMC-pCN-GM) and SMC-GM (Alg. 3)
   adjoint    gradient of the potential by an adjoint solve
+  example1   the paper's multi-modal L^2 example (Sec. 3.1) and its exact mixture posterior
   linear     closed-form linear-Gaussian posterior (test target)
   quadrature brute-force posterior moments for tiny problems (test target)
 """
