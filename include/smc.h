@@ -84,6 +84,27 @@ typedef struct {
     int32_t precond;        /* SMC_PRECOND_AUTO or SMC_PRECOND_JACOBI */
 } smc_problem_desc;
 
+/* Problem without a PDE: the paper's Example 1 (Sec. 3.1), a mixture likelihood in L^2(0, 1).
+ * Prior N(0, (I - alpha Delta)^{-2}) with the Neumann cosine eigenpairs phi_0 = 1,
+ * phi_k = sqrt(2) cos(k pi x), lambda_k = (1 + alpha k^2 pi^2)^{-2}, k = 0 .. K-1, so
+ * u = sum_k sqrt(lambda_k) xi_k phi_k; likelihood (eq. (example1phi))
+ *   exp(-Phi(u)) = sum_i exp(-|u - f_i|^2 / (2 sigma^2)),
+ * each f_i given by its coefficients c[i][k] = <f_i, phi_k> (f_i in the span of the K modes),
+ * so Phi(xi) = -log sum_i exp(-sum_k (sqrt(lambda_k) xi_k - c_ik)^2 / (2 sigma^2)).
+ * The active modes are 0 .. kr-1 (lambda decreases with k).  Such a problem supports the
+ * prior draw, smc_phi_batch, the pCN-GM moves and stages, smc_gm_fit, smc_gm_draw, tempering
+ * and resampling; calls that need a grid (synthesis, forward maps, gradients, tiles, level
+ * maps) return SMC_E_INVAL. */
+typedef struct {
+    int32_t K;          /* modes, 1..1024 */
+    int32_t kr;         /* modes the mixture moves, 1..min(64, K) */
+    double alpha;       /* prior operator I - alpha Delta, alpha > 0 (0.01 in the paper) */
+    int32_t n_terms;    /* likelihood terms, 1..16 */
+    const double* c;    /* host [n_terms][K] coefficients of the centres, finite */
+    double sigma;       /* > 0 */
+    int64_t n_max;      /* largest particle count any call will pass, 1..2^24 */
+} smc_l2mix_desc;
+
 /* Preconditioner of the conjugate gradients.  AUTO: the fast-Poisson (sine-transform)
  * preconditioner on the matrix cores for FP32 solves on 32^2, 64^2 and 128^2 grids, Jacobi
  * scaling elsewhere; JACOBI: Jacobi scaling everywhere. */
@@ -107,10 +128,17 @@ typedef struct {
 /* Create a problem: copies the definition, tabulates the prior and the grids on the device,
  * allocates all workspace for n_max particles.  *out is set only on SMC_OK. */
 int smc_problem_create(const smc_problem_desc* desc, smc_problem* out);
+/* Create a problem of the L^2 mixture kind (smc_l2mix_desc); *out is set only on SMC_OK. */
+int smc_problem_create_l2mix(const smc_l2mix_desc* desc, smc_problem* out);
 /* Free a problem and its workspace (waits for the device).  NULL is ignored. */
 void smc_problem_destroy(smc_problem p);
 /* Text of the last non-OK status returned on the calling thread. */
 const char* smc_last_error(void);
+/* The 53-bit integer (w0 >> 5) 2^26 + (w1 >> 6) of the Philox4x32-10 words w of counter
+ * (block, word, ctr lo, ctr hi) under key (seed lo, seed hi): the kernels' generator, computed on
+ * the host for draws a caller passes in (the resampling uniform u53 of smc_resample; the drivers
+ * use block 0x80000001, word 0, counter stage * 2^20).  Pure host arithmetic. */
+uint64_t smc_philox_u53(uint64_t seed, uint64_t ctr, uint32_t block, uint32_t word);
 /* K, the active mode list (host out [kr]) and the observation count; any pointer may be NULL. */
 int smc_problem_info(smc_problem p, int32_t* K, int32_t* active, int32_t* n_obs);
 /* Synchronise `stream`, return the device status word in *flags (host) and clear it if
@@ -137,6 +165,13 @@ int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, do
  *   iters  [N] out, conjugate-gradient iterations, -1 when not converged; may be NULL */
 int smc_forward_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level,
                       int32_t prec, double* G, int32_t* iters, smc_stream stream);
+
+/* Potential of each particle for either problem kind: the forward map and Phi = |G - y|^2 /
+ * (2 sigma^2) (one solve each; level and prec as in smc_forward_batch), or the closed form of
+ * an L^2 mixture problem (level must be NULL there; prec is ignored).
+ *   xi [N][K] in, phi [N] out (+inf where a solve does not converge), iters [N] out or NULL. */
+int smc_phi_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level, int32_t prec,
+                  double* phi, int32_t* iters, smc_stream stream);
 
 /* Potential Phi = |G - y|^2 / (2 sigma^2) (Sec. 2.1): phi[N] out, +inf for non-finite rows. */
 int smc_potential(smc_problem p, int64_t N, const double* G, double* phi, smc_stream stream);

@@ -19,9 +19,11 @@ stage whose temperature reaches 1 (Alg. 3 runs its loop one step further than Al
 both stop at the same final temperature here).
 
 Random numbers: the prior draw uses counter 0; stage s uses counters
-s * 2^20 + m for its moves and draws its resampling uniform from block
-RESAMPLE_BLOCK at counter s * 2^20.  SMC-GM's fit and draw at stage s both use
-counter s * 2^20 (different blocks).
+s * 2^20 + m for its moves, draws its resampling uniform from block
+RESAMPLE_BLOCK at counter s * 2^20, and seeds its mixture fit (gmfit.fit_philox)
+at counter s * 2^20.  SMC-GM's fit and draw at stage s both use counter s * 2^20
+(different blocks).  A run is therefore a function of its seed alone, and the GPU
+drivers, which follow the same layout, replay it.
 """
 import numpy as np
 
@@ -69,7 +71,7 @@ def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stag
         if M == 1:
             gm = pcn_gm(K, active)
         else:
-            logw, mean, var = gmfit.fit(xi[:, active], M, seed=seed + s)
+            logw, mean, var, _ = gmfit.fit_philox(xi[:, active], M, seed, s * STAGE_STRIDE)
             gm = GM(logw, mean, var, active, K)
         xi, phi, n_acc = gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
                                      phi_fn=f)

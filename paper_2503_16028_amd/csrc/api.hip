@@ -64,9 +64,29 @@ static void free_problem(Problem& P) {
     f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.ws_list); f(P.ws_counters); f(P.flags); f(P.stats);
     f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers);
+    f(P.mix_c);
 }
 
 extern "C" const char* smc_last_error(void) { return g_err.c_str(); }
+
+// Philox4x32-10 on the host (the kernels' generator, for the few draws the host hands to a call).
+extern "C" uint64_t smc_philox_u53(uint64_t seed, uint64_t ctr, uint32_t block, uint32_t word) {
+    uint32_t c0 = block, c1 = word, c2 = (uint32_t)ctr, c3 = (uint32_t)(ctr >> 32);
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return ((uint64_t)(c0 >> 5) << 26) | (uint64_t)(c1 >> 6);
+}
 
 extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     if (!d || !out) return fail(SMC_E_INVAL, "desc and out must not be NULL");
@@ -226,6 +246,71 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
         ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * pe));
         ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
     }
+    ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
+    ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
+    ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
+    ck(hipMemset(P.flags, 0, sizeof(int32_t)));
+    ck(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        free_problem(P);
+        delete ps;
+        return fail(e == hipErrorOutOfMemory ? SMC_E_NOMEM : SMC_E_HIP, "problem setup: %s", hipGetErrorString(e));
+    }
+    *out = ps;
+    return SMC_OK;
+}
+
+extern "C" int smc_problem_create_l2mix(const smc_l2mix_desc* d, smc_problem* out) {
+    if (!d || !out) return fail(SMC_E_INVAL, "desc and out must not be NULL");
+    if (d->K < 1 || d->K > 1024) return fail(SMC_E_INVAL, "K must be 1..1024");
+    if (d->kr < 1 || d->kr > MAX_KR || d->kr > d->K) return fail(SMC_E_INVAL, "kr must be 1..min(64, K)");
+    if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return fail(SMC_E_INVAL, "alpha must be positive");
+    if (d->n_terms < 1 || d->n_terms > MAX_TERMS) return fail(SMC_E_INVAL, "n_terms must be 1..%d", MAX_TERMS);
+    if (!d->c) return fail(SMC_E_INVAL, "c must not be NULL");
+    for (int64_t i = 0; i < (int64_t)d->n_terms * d->K; ++i)
+        if (!std::isfinite(d->c[i])) return fail(SMC_E_INVAL, "c[%lld] is not finite", (long long)i);
+    if (!(d->sigma > 0.0) || !std::isfinite(d->sigma)) return fail(SMC_E_INVAL, "sigma must be positive");
+    if (d->n_max < 1 || d->n_max > (1 << 24)) return fail(SMC_E_INVAL, "n_max must be 1..2^24");
+
+    smc_problem_s* ps = new smc_problem_s();
+    Problem& P = ps->P;
+    (void)hipGetDevice(&ps->device);
+    P.kind = KIND_L2MIX;
+    P.dim = 1;
+    P.n_levels = 0;
+    P.kl = d->K;
+    P.K = d->K;
+    P.kr = d->kr;
+    P.n_obs = 0;
+    P.n_terms = d->n_terms;
+    P.sigma = d->sigma;
+    P.n_max = d->n_max;
+    // lambda_k = (1 + alpha k^2 pi^2)^{-2} decreases with k: the active modes are 0 .. kr-1
+    std::vector<double> sl(P.K);
+    for (int k = 0; k < P.K; ++k) sl[k] = 1.0 / (1.0 + d->alpha * M_PI * M_PI * (double)k * k);
+    std::vector<int32_t> act(P.kr), slot(P.K, -1);
+    for (int a = 0; a < P.kr; ++a) {
+        act[a] = a;
+        slot[a] = a;
+        P.active_h[a] = a;
+    }
+    hipError_t e = hipSuccess;
+    auto ck = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    ck(prepare_kernels());
+    ck(hipDeviceGetAttribute(&P.n_cu, hipDeviceAttributeMultiprocessorCount, ps->device));
+    ck(upload(&P.sqrt_lam, sl.data(), P.K));
+    ck(upload(&P.active, act.data(), act.size()));
+    ck(upload(&P.slot, slot.data(), slot.size()));
+    ck(upload(&P.mix_c, d->c, (size_t)P.n_terms * P.K));
+    const int64_t Nm = P.n_max;
+    ck(hipMalloc((void**)&P.ws_v, sizeof(double) * Nm * P.K));
+    ck(hipMalloc((void**)&P.ws_logr, sizeof(double) * Nm));
+    ck(hipMalloc((void**)&P.ws_phinew, sizeof(double) * Nm));
+    ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
+    ck(hipMalloc((void**)&P.ws_fit_d2, sizeof(double) * Nm));
+    ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * GM_PAR));
+    ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * MAX_M * (1 + 2 * MAX_KR)));
+    ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
     ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
@@ -433,8 +518,11 @@ static hipError_t forward_levels(smc_problem_s* ps, int prec, int64_t N, const d
 
 static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, const Solve& o,
                           hipStream_t s) {
-    if (o.level) return forward_levels(ps, prec, N, xi, o, s);
     const Problem& P = ps->P;
+    if (P.kind == KIND_L2MIX)   // the potential is a closed form of xi: no synthesis, no solve
+        return launch_l2mix_phi(N, P.K, P.sqrt_lam, P.mix_c, P.n_terms, 0.5 / (P.sigma * P.sigma), xi, o.phi,
+                                o.iters, s);
+    if (o.level) return forward_levels(ps, prec, N, xi, o, s);
     hipError_t e = synth(P, level, N, xi, P.ws_e, P.e_stride, true, s);
     if (e != hipSuccess) return e;
     const Level& L = P.lv[level];
@@ -470,9 +558,30 @@ static hipError_t gradient(const Problem& P, int level, int64_t N, const double*
                               P.kl, P.K, grad, N, s);
 }
 
+extern "C" int smc_phi_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level, int32_t prec,
+                             double* phi, int32_t* iters, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (int r = check_n(P, N)) return r;
+    if (N > 0 && (!xi || !phi)) return fail(SMC_E_INVAL, "xi and phi must not be NULL");
+    if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
+    if (level) {
+        if (int r = check_levels(P)) return r;
+        if (N > 0) HIPCHK(launch_plan(N, level, level_table(P), P.ws_list, P.ws_counters, P.flags,
+                                      (hipStream_t)stream));
+    }
+    Solve o;
+    o.level = level;
+    o.phi = phi;
+    o.iters = iters;
+    HIPCHK(forward(p, 0, prec, N, xi, o, (hipStream_t)stream));
+    return SMC_OK;
+}
+
 extern "C" int smc_forward_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level,
                                  int32_t prec, double* G, int32_t* iters, smc_stream stream) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (p->P.kind != KIND_DARCY) return fail(SMC_E_INVAL, "this problem has no observation operator");
     if (int r = check_n(p->P, N)) return r;
     if (N > 0 && (!xi || !G)) return fail(SMC_E_INVAL, "xi and G must not be NULL");
     if (prec != SMC_FP64 && prec != SMC_FP32_REFINE) return fail(SMC_E_INVAL, "unknown precision %d", prec);
@@ -529,6 +638,7 @@ extern "C" int smc_value_and_grad(smc_problem p, int64_t N, const double* xi, in
 
 extern "C" int smc_potential(smc_problem p, int64_t N, const double* G, double* phi, smc_stream stream) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    if (p->P.kind != KIND_DARCY) return fail(SMC_E_INVAL, "this problem has no observations (use smc_phi_batch)");
     if (int r = check_n(p->P, N)) return r;
     if (N > 0 && (!G || !phi)) return fail(SMC_E_INVAL, "G and phi must not be NULL");
     HIPCHK(launch_potential(N, p->P.n_obs, G, p->P.y, 0.5 / (p->P.sigma * p->P.sigma), phi, (hipStream_t)stream));

@@ -12,6 +12,9 @@ constexpr int MAX_OBS = 64;
 constexpr int MAX_M = 16;
 constexpr int MAX_KR = 64;
 constexpr int GM_PAR = 2 * MAX_M + 4 * MAX_M * MAX_KR;   // doubles in one mixture-fit parameter block
+constexpr int MAX_TERMS = 16;        // terms of an L^2 mixture likelihood
+constexpr int KIND_DARCY = 0;        // forward map: Darcy solve, observations at nodes
+constexpr int KIND_L2MIX = 1;        // no forward map: mixture likelihood in L^2 on the coefficients
 constexpr int KLP = 32;          // 2D modes per axis, padded, in the synthesis tiles
 constexpr uint32_t UNIFORM_BLOCK = 0x80000000u;
 
@@ -25,7 +28,10 @@ struct Level {
 };
 
 struct Problem {
+    int kind = KIND_DARCY;
     int dim = 0, n_levels = 0, kl = 0, K = 0, kr = 0, n_obs = 0;
+    int n_terms = 0;             // KIND_L2MIX: likelihood terms
+    double* mix_c = nullptr;     // KIND_L2MIX: [n_terms][K] coefficients of the centres f_i
     Level lv[MAX_LEVELS];
     int n_big = 0;               // largest grid
     double sigma = 1, f = 1, tol64 = 1e-10, tol_inner = 1e-5;
@@ -239,6 +245,8 @@ hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t
 hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
                          const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s);
 hipError_t prepare_kernels();
+hipError_t launch_l2mix_phi(int64_t N, int K, const double* sqrt_lam, const double* c, int T, double inv2s2,
+                            const double* xi, double* phi, int32_t* iters, hipStream_t s);
 hipError_t launch_gm_draw(int64_t N, int K, const int32_t* slot, uint64_t seed, uint64_t ctr, int M, int kr,
                           const double* logw, const double* mean, const double* scale, double* v, hipStream_t s);
 

@@ -10,9 +10,10 @@ SMC-pCN-GM, per stage, in the order S^N P_{j+1} L_{j+1} of Sec. 2.2 (eq. (decide
 SMC-GM replaces the moves by smc_gm_draw: every particle becomes an independent draw from the
 fitted mixture, accepted without a test, and its potential is what the next stage re-weights.
 Both loops end when the cumulative temperature reaches 1.  Every step runs on the device; the
-host reads back the temperature (and the acceptance count) once per stage.
+host reads back the temperature (and the acceptance count) once per stage.  Random numbers:
+stage s draws its resampling uniform from Philox block 0x80000001 and its moves, mixture fit and
+mixture draws at counters s * 2^20 (+ move index), so a run is a function of its seed alone.
 """
-import numpy as np
 import torch
 
 from . import smc
@@ -50,7 +51,6 @@ class SMCSampler:
         self.xi2 = torch.empty(N, K, **f64)
         self.phi = torch.empty(N, **f64)
         self.phi2 = torch.empty(N, **f64)
-        self.G = torch.empty(N, problem.n_obs, **f64)
         self.W = torch.empty(N, **f64)
         self.tau = torch.zeros(1, **f64)
         self.tau_new = torch.zeros(1, **f64)
@@ -68,8 +68,7 @@ class SMCSampler:
     def initialise(self):
         p, N = self.p, self.N
         smc.smc_prior_sample(p, N, self.seed, 0, self.xi)
-        smc.smc_forward_batch(p, N, self.xi, None, self.prec, self.G)
-        smc.smc_potential(p, N, self.G, self.phi)
+        smc.smc_phi_batch(p, N, self.xi, None, self.prec, self.phi)
 
     def mixture(self):
         if self.M == 1:
@@ -82,7 +81,7 @@ class SMCSampler:
         self.stage += 1
         base = self.stage * STAGE_STRIDE
         smc.smc_temper(N, self.phi, self.tau, self.ess_frac, self.h, self.tau_new, self.W, self.log_z, self.flags)
-        u53 = int(np.random.default_rng([self.seed, self.stage]).integers(0, 1 << 53))
+        u53 = smc.smc_philox_u53(self.seed, base)
         smc.smc_resample(N, self.W, u53, self.idx, self.flags)
         smc.smc_gather(N, p.K, self.idx, self.xi, self.phi, self.xi2, self.phi2)
         self.xi, self.xi2 = self.xi2, self.xi
@@ -126,7 +125,7 @@ class SMCGMSampler(SMCSampler):
         self.stage += 1
         base = self.stage * STAGE_STRIDE
         smc.smc_temper(N, self.phi, self.tau, self.ess_frac, self.h, self.tau_new, self.W, self.log_z, self.flags)
-        u53 = int(np.random.default_rng([self.seed, self.stage]).integers(0, 1 << 53))
+        u53 = smc.smc_philox_u53(self.seed, base)
         smc.smc_resample(N, self.W, u53, self.idx, self.flags)
         smc.smc_gather(N, p.K, self.idx, self.xi, self.phi, self.xi2, self.phi2)
         self.xi, self.xi2 = self.xi2, self.xi

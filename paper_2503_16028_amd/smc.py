@@ -41,6 +41,11 @@ class GMDesc(ctypes.Structure):
     _fields_ = [("M", c_i32), ("kr", c_i32), ("logw", c_vp), ("mean", c_vp), ("scale", c_vp)]
 
 
+class L2MixDesc(ctypes.Structure):
+    _fields_ = [("K", c_i32), ("kr", c_i32), ("alpha", c_dbl), ("n_terms", c_i32), ("c", ctypes.POINTER(c_dbl)),
+                ("sigma", c_dbl), ("n_max", c_i64)]
+
+
 class StageDesc(ctypes.Structure):
     _fields_ = [("n_groups", c_i32), ("M", c_i32), ("kr", c_i32), ("logw", c_vp), ("mean", c_vp), ("scale", c_vp),
                 ("beta", c_vp), ("tau", c_vp), ("ctr", c_vp), ("seed", c_u64)]
@@ -48,8 +53,11 @@ class StageDesc(ctypes.Structure):
 
 _SIGS = {
     "smc_problem_create": (c_i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(c_vp)]),
+    "smc_problem_create_l2mix": (c_i32, [ctypes.POINTER(L2MixDesc), ctypes.POINTER(c_vp)]),
     "smc_problem_destroy": (None, [c_vp]),
+    "smc_phi_batch": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "smc_last_error": (ctypes.c_char_p, []),
+    "smc_philox_u53": (c_u64, [c_u64, c_u64, ctypes.c_uint32, ctypes.c_uint32]),
     "smc_problem_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "smc_status_flags": (c_i32, [c_vp, c_vp, ctypes.POINTER(c_i32), c_i32]),
     "smc_prior_sample": (c_i32, [c_vp, c_i64, c_u64, c_u64, c_vp, c_vp]),
@@ -160,10 +168,13 @@ class Problem:
         _check(L.smc_problem_create(ctypes.byref(desc), ctypes.byref(handle)))
         self.handle = handle
         self.n_max = int(n_max)
+        self._info(desc.kr)
+
+    def _info(self, kr):
         K, n_obs = c_i32(), c_i32()
         act = (c_i32 * 64)()
-        _check(L.smc_problem_info(handle, ctypes.byref(K), act, ctypes.byref(n_obs)))
-        self.K, self.n_obs, self.kr = K.value, n_obs.value, desc.kr
+        _check(lib().smc_problem_info(self.handle, ctypes.byref(K), act, ctypes.byref(n_obs)))
+        self.K, self.n_obs, self.kr = K.value, n_obs.value, kr
         self.active = [act[k] for k in range(self.kr)]
 
     def close(self):
@@ -176,6 +187,31 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class L2MixProblem(Problem):
+    """An smc_problem of the L^2 mixture kind (no PDE): c is [n_terms][K] (numpy or list)."""
+
+    def __init__(self, K, kr, alpha, c, sigma, n_max):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1, int(K)))
+        self._c = (c_dbl * c.size)(*c.ravel().tolist())
+        desc = L2MixDesc()
+        desc.K, desc.kr, desc.alpha = int(K), int(kr), float(alpha)
+        desc.n_terms, desc.c, desc.sigma, desc.n_max = c.shape[0], self._c, float(sigma), int(n_max)
+        handle = c_vp()
+        _check(lib().smc_problem_create_l2mix(ctypes.byref(desc), ctypes.byref(handle)))
+        self.handle = handle
+        self.dim, self.grids, self.n_max = 1, [], int(n_max)
+        self._info(int(kr))
+
+
+RESAMPLE_BLOCK = 0x80000001
+
+
+def smc_philox_u53(seed, ctr, block=RESAMPLE_BLOCK, word=0):
+    """53-bit integer uniform of the library's generator (host arithmetic)."""
+    return int(lib().smc_philox_u53(int(seed), int(ctr), int(block), int(word)))
 
 
 def smc_status_flags(problem, stream=None, clear=True):
@@ -201,6 +237,14 @@ def smc_forward_batch(problem, N, xi, level, prec, G, iters=None, stream=None):
                                    _ptr(level, torch.int32, N, "level", optional=True), prec,
                                    _ptr(G, torch.float64, N * problem.n_obs, "G"),
                                    _ptr(iters, torch.int32, N, "iters", optional=True), _stream(stream)))
+
+
+def smc_phi_batch(problem, N, xi, level, prec, phi, iters=None, stream=None):
+    """Potential of each particle (forward map and Phi, or the closed form of an L^2 mixture)."""
+    _check(lib().smc_phi_batch(problem.handle, N, _ptr(xi, torch.float64, N * problem.K, "xi"),
+                               _ptr(level, torch.int32, N, "level", optional=True), prec,
+                               _ptr(phi, torch.float64, N, "phi"), _ptr(iters, torch.int32, N, "iters", optional=True),
+                               _stream(stream)))
 
 
 def smc_potential(problem, N, G, phi, stream=None):

@@ -24,7 +24,7 @@ def libsmc():
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(smc_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|uint64_t|const char\*)\s+(smc_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_calls():
@@ -104,3 +104,16 @@ def test_tile_candidates():
     assert smc.smc_tile_candidates(256) == [0]
     with pytest.raises(smc.SMCError):
         smc.smc_tile_candidates(16)
+
+
+def test_host_philox_matches_the_oracle_generator(libsmc):
+    """smc_philox_u53 (host arithmetic) against the oracle's Philox4x32-10 and its 53-bit integer."""
+    from oracle import gmfit, philox
+    from oracle.smc import RESAMPLE_BLOCK, resample_u53
+    from paper_2503_16028_amd import smc
+    for seed, ctr in [(0, 0), (3, 1 << 20), (2 ** 40 + 7, 5 << 20), (2 ** 64 - 1, 2 ** 63 + 5)]:
+        assert smc.smc_philox_u53(seed, ctr, RESAMPLE_BLOCK, 0) == resample_u53(seed, ctr)
+        for m in (0, 1, 15):
+            assert smc.smc_philox_u53(seed, ctr, gmfit.KMPP_BLOCK, m) == gmfit.kmpp_u53(seed, ctr, m)
+        w = philox.philox4x32_10([5, 9, ctr & philox.MASK32, ctr >> 32], philox._key(seed))
+        assert smc.smc_philox_u53(seed, ctr, 5, 9) == (int(w[0]) >> 5) * (1 << 26) + (int(w[1]) >> 6)
