@@ -142,6 +142,35 @@ def smc_gm_variant(dev, N=4096, M=8, stages=3):
             "gm_fit_ms_N4096_M8_50em": fit_ms}
 
 
+def example1_variant(dev, N=20000, M=8, chain=200, K=64, sigma=0.1):
+    """The paper's Example 1 (Sec. 3.1, no PDE): whole SMC-GM and SMC-pCN-GM runs of N = 20000
+    particles (the paper's sample count) on the four-term L^2 likelihood with K = 64 cosine modes;
+    SMC-pCN-GM with the paper's chain length of 200 moves per stage."""
+    import numpy as np
+    import torch
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCGMSampler, SMCSampler
+    c = np.zeros((4, K))                  # f = cos(pi x), -cos(pi x), cos(2 pi x), cos(3 pi x) on phi_k = sqrt(2) cos(k pi x)
+    for i, (k, sg) in enumerate(((1, 1.0), (1, -1.0), (2, 1.0), (3, 1.0))):
+        c[i, k] = sg / np.sqrt(2.0)
+    p = smc.L2MixProblem(K, K, 0.01, c, sigma, N)
+    out = {}
+    for name, make in (("smc_gm", lambda: SMCGMSampler(p, N, M, seed=1, device=dev)),
+                       ("smc_pcngm_chain200", lambda: SMCSampler(p, N, M, chain, beta0=0.5, seed=1, device=dev))):
+        make().run()                      # warm-up run
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = make().run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["example1_%s_N20000_samples_per_s" % name] = N / dt
+        out["example1_%s_run_s" % name] = dt
+        out["example1_%s_stages" % name] = len(r["history"])
+        if name != "smc_gm":
+            out["example1_%s_moves_per_s" % name] = N * chain * len(r["history"]) / dt
+    return out
+
+
 def mixed_variant(dev, counts=(4096, 3072, 1024), n_moves=20, stages=2):
     """Three samplers on 64^2, 128^2 and 256^2 (N = 8192) moved by one captured stage graph."""
     import numpy as np
@@ -271,6 +300,7 @@ def main():
     if not args.no_variants:
         variants.update(pcnl_variant(dev))
         variants.update(smc_gm_variant(dev))
+        variants.update(example1_variant(dev))
         variants.update(mixed_variant(dev))
         t64, prof64, _ = stage_loop(smc.SMC_FP64, 1, 0, 4)
         variants["fp64_batched_moves_per_s"] = N * 4 / t64

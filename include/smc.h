@@ -305,7 +305,8 @@ int smc_temper(int64_t N, const double* phi, const double* tau_in, double ess_fr
  *   q_n = floor(W_n 2^53), C_n = q_0 + ... + q_n, Q = C_{N-1},
  *   idx_i = min{n : C_n > floor((i 2^53 + u53) Q / (N 2^53))},  i = 0..N-1.
  * u53 in [0, 2^53) is the uniform times 2^53.  idx[N] out (nondecreasing).  All-zero weights
- * set SMC_FLAG_BADWEIGHTS in *flags (device, may be NULL) and give idx = 0..N-1.  N <= 16384. */
+ * set SMC_FLAG_BADWEIGHTS in *flags (device, may be NULL) and give idx = 0..N-1.
+ * 1 <= N <= 2^24. */
 int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags,
                  smc_stream stream);
 

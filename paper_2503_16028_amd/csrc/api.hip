@@ -978,7 +978,7 @@ extern "C" int smc_temper(int64_t N, const double* phi, const double* tau_in, do
 
 extern "C" int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags,
                             smc_stream stream) {
-    if (N < 1 || N > 16384) return fail(SMC_E_INVAL, "N must be 1..16384");
+    if (N < 1 || N > (1ll << 24)) return fail(SMC_E_INVAL, "N must be 1..2^24");
     if (!W || !idx) return fail(SMC_E_INVAL, "W and idx must not be NULL");
     if (u53 >= (1ull << 53)) return fail(SMC_E_INVAL, "u53 must be below 2^53");
     HIPCHK(launch_resample(N, W, u53, idx, flags, (hipStream_t)stream));

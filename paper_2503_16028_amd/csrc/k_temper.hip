@@ -100,59 +100,59 @@ hipError_t launch_temper(int64_t N, const double* phi, const double* tau_in, dou
 
 // Systematic resampling on integers: q_n = floor(W_n 2^53), inclusive scan C, Q = C_{N-1};
 // idx_i = min{n : C_n > floor(T_i Q / D)} with T_i = i 2^53 + u53 and D = N 2^53.  For an
-// integer C, C > floor(x) iff C > x, so the test is C_n D > T_i Q, evaluated exactly on
-// 128-bit products.  The scan is exact, so the result does not depend on summation order.
-constexpr int RS_MAX = 16384;
+// integer C, C > floor(x) iff C > x, so output i belongs to particle n exactly when
+// C_{n-1} D <= T_i Q < C_n D: every particle owns a contiguous range of outputs, starting at
+//   first(C_{n-1}) = min{i : T_i Q >= C_{n-1} D} = ceil(C_{n-1} N / Q - u53 / 2^53),
+// evaluated exactly on 128-bit integers.  One workgroup; thread t owns a contiguous chunk of
+// particles: their integer weights are summed, the thread totals scanned, and a second pass
+// writes each particle's range.  Integer sums make the result independent of summation order,
+// and no CDF is stored, so N is limited only by the 32-bit output indices.
+__device__ __forceinline__ uint64_t qweight53(double w) {
+    return (w > 0.0 && w <= 1.0) ? (uint64_t)(w * 9007199254740992.0) : 0ull;
+}
+
+// min{i >= 0 : (i 2^53 + u53) Q >= C N 2^53} = q + [r 2^53 > u53 Q], where C N = q Q + r
+// (0 <= r < Q); q <= N, found from a double estimate and corrected exactly.
+__device__ __forceinline__ int64_t first_output(uint64_t C, int64_t N, uint64_t Q, uint64_t u53) {
+    const unsigned __int128 A = (unsigned __int128)C * (uint64_t)N;
+    int64_t q = (int64_t)floor((double)C * (double)N / (double)Q);
+    if (q < 0) q = 0;
+    while ((unsigned __int128)(q + 1) * Q <= A) ++q;
+    while (q > 0 && (unsigned __int128)q * Q > A) --q;
+    const unsigned __int128 r = A - (unsigned __int128)q * Q;
+    return q + ((r << 53) > (unsigned __int128)u53 * Q ? 1 : 0);
+}
 
 __global__ __launch_bounds__(TB) void resample_kernel(int64_t N, const double* __restrict__ W, uint64_t u53,
                                                       int32_t* __restrict__ idx, int32_t* __restrict__ flags) {
-    __shared__ uint64_t C[RS_MAX];
     __shared__ uint64_t part[TB];
     const int tid = threadIdx.x;
-    const int per = (int)((N + TB - 1) / TB);
-    const int64_t beg = (int64_t)tid * per;
+    const int64_t per = (N + TB - 1) / TB;
+    const int64_t beg = tid * per, end = beg + per < N ? beg + per : N;
     uint64_t run = 0;
-    for (int k = 0; k < per; ++k) {
-        const int64_t n = beg + k;
-        if (n < N) {
-            const double w = W[n];
-            const uint64_t q = (w > 0.0 && w <= 1.0) ? (uint64_t)(w * 9007199254740992.0) : 0ull;
-            run += q;
-            C[n] = run;
-        }
-    }
+    for (int64_t n = beg; n < end; ++n) run += qweight53(W[n]);
     part[tid] = run;
     __syncthreads();
-    // exclusive scan of the per-thread totals (Hillis-Steele on 1024 entries)
+    // inclusive scan of the per-thread totals (Hillis-Steele on TB entries)
     for (int off = 1; off < TB; off <<= 1) {
         const uint64_t v = (tid >= off) ? part[tid - off] : 0ull;
         __syncthreads();
         part[tid] += v;
         __syncthreads();
     }
-    const uint64_t base = (tid > 0) ? part[tid - 1] : 0ull;
-    for (int k = 0; k < per; ++k) {
-        const int64_t n = beg + k;
-        if (n < N) C[n] += base;
-    }
-    __syncthreads();
-    const uint64_t Q = C[N - 1];
+    const uint64_t Q = part[TB - 1];
     if (Q == 0) {
         for (int64_t i = tid; i < N; i += TB) idx[i] = (int32_t)i;
         if (tid == 0 && flags) atomicOr(flags, SMC_FLAG_BADWEIGHTS);
         return;
     }
-    const unsigned __int128 D = (unsigned __int128)N << 53;
-    for (int64_t i = tid; i < N; i += TB) {
-        const unsigned __int128 t = ((unsigned __int128)i << 53) + u53;
-        const unsigned __int128 rhs = t * Q;
-        int64_t lo = 0, hi = N - 1;   // C[N-1] D = Q D > rhs since t < D
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((unsigned __int128)C[mid] * D > rhs) hi = mid;
-            else lo = mid + 1;
-        }
-        idx[i] = (int32_t)lo;
+    uint64_t C = (tid > 0) ? part[tid - 1] : 0ull;   // C_{beg-1}
+    int64_t lo = first_output(C, N, Q, u53);
+    for (int64_t n = beg; n < end; ++n) {
+        C += qweight53(W[n]);
+        const int64_t hi = first_output(C, N, Q, u53);
+        for (int64_t i = lo; i < hi; ++i) idx[i] = (int32_t)n;
+        lo = hi;
     }
 }
 

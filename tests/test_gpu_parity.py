@@ -333,7 +333,7 @@ def test_temper_edge_cases():
     assert flags.item() & smc.FLAG_NONFINITE
 
 
-@pytest.mark.parametrize("N", [1, 7, 1000, 4096, 16384])
+@pytest.mark.parametrize("N", [1, 7, 1000, 4096, 16384, 20000, 1 << 20])
 @pytest.mark.parametrize("kind", ["dirichlet", "sparse", "one", "uniform"])
 def test_resample_bit_exact(N, kind):
     from paper_2503_16028_amd import smc
