@@ -48,7 +48,7 @@ def test_host_validation_rejects_without_launching(libsmc):
     assert libsmc.smc_temper(0, null, null, 0.5, null, null, null, null, null, null) == -1
     assert b"N must be" in libsmc.smc_last_error()
     assert libsmc.smc_temper(4, c_vp(8), c_vp(8), 1.5, c_vp(8), c_vp(8), c_vp(8), c_vp(8), null, null) == -1
-    assert libsmc.smc_resample(16385, c_vp(8), 0, c_vp(8), null, null) == -1
+    assert libsmc.smc_resample((1 << 24) + 1, c_vp(8), 0, c_vp(8), null, null) == -1
     assert libsmc.smc_resample(4, c_vp(8), 1 << 53, c_vp(8), null, null) == -1
     assert libsmc.smc_gather(4, 8, c_vp(8), c_vp(16), null, c_vp(16), null, null) == -1   # aliasing
     assert libsmc.smc_problem_create(None, None) == -1
