@@ -632,7 +632,10 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
                 rr = block_sum<NW>(tacc, red1);
                 rz = rr;
             }
-            const double target = a.tol_inner * a.tol_inner * rr;
+            // the inner solve reduces its residual by tol_inner, or only as far as the outer tolerance
+            // still needs (a margin of 10 for the Jacobi-scaled norm), whichever is less work
+            const double red = fmin(0.5, fmax(a.tol_inner, 0.1 * a.tol64 * fnorm / sqrt(rr64)));
+            const double target = red * red * rr;
             bool broke = false;
             while (rr > target) {
                 if (total >= a.max_iter) break;
@@ -948,7 +951,10 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                 }
                 rz = block_sum<NW>(zacc, red2);
             }
-            const double target = a.tol_inner * a.tol_inner * rr;
+            // the inner solve reduces its residual by tol_inner, or only as far as the outer tolerance
+            // still needs (a margin of 10 for the Jacobi-scaled norm), whichever is less work
+            const double red = fmin(0.5, fmax(a.tol_inner, 0.1 * a.tol64 * fnorm / sqrt(rr64)));
+            const double target = red * red * rr;
             bool broke = false;
             if constexpr (DST) {
                 // Per iteration four passes over the global vectors: the stencil (t p of the
