@@ -136,7 +136,7 @@ def _ptr(t, dtype, numel=None, name="tensor", optional=False):
 class Problem:
     """An smc_problem built from a problem definition (dict with the JSON fields)."""
 
-    def __init__(self, d, n_max, grids=None, tol64=1e-10, tol_inner=1e-5, max_iter=None, max_sweeps=8,
+    def __init__(self, d, n_max, grids=None, tol64=1e-10, tol_inner=1e-3, max_iter=None, max_sweeps=8,
                  precond=PRECOND_AUTO):
         L = lib()
         grids = list(grids if grids is not None else d["grids"])
