@@ -748,6 +748,13 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf
 constexpr int D256_LD = 256 + 8;
 constexpr int D256_BYTES = 256 * D256_LD * 2;
 
+// LDS named at module level: the mixed-grid solve's bodies and the 256^2 transform below are
+// functions of their own (register-allocated apart from their callers), and LDS they name directly
+// keeps its LDS instructions, where a pointer passed in would turn into generic accesses.
+constexpr int MIXED_SMEM = cmax(onchip_smem<float, 128, 16, true>(),
+                                cmax(onchip_smem<float, 64, 4, true>(), onchip_smem<double, 64, 4, false>()));
+__shared__ __align__(16) unsigned char g_mixed_smem[MIXED_SMEM];
+
 // With `staged`, X already holds bf16(r) (written by the caller's residual update); with `rz`,
 // the thread's share of sum r z is accumulated while z is stored.
 __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, __bf16* X,
@@ -806,6 +813,17 @@ __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float*
     __syncthreads();   // z complete for every thread of the workgroup
 }
 
+// The 256^2 transform as a function of its own, on the module-level buffer both 256^2 solvers
+// stage X in: inlined into the CG loop it competes for that loop's registers and both spill.
+// Returns this thread's share of r.z when `staged` (r already in X as bf16), else 0.
+static_assert(D256_BYTES <= MIXED_SMEM, "256^2 transform LDS");
+__device__ __noinline__ double dst256_precondition(const float* r, float* z, const __bf16* S, const float* lam,
+                                                   int staged) {
+    double rz = 0.0;
+    dst256_apply(r, z, reinterpret_cast<__bf16*>(g_mixed_smem), S, lam, staged != 0, staged ? &rz : nullptr);
+    return rz;
+}
+
 __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
                                                             const __bf16* __restrict__ Stab,
                                                             const float* __restrict__ lamtab) {
@@ -846,7 +864,8 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
     int napp = 0;
     auto precondition = [&]() {   // zv = L^{-1} rv
         if constexpr (DST) {
-            dst256_apply(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), X, Stab, lamtab);
+            (void)dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), Stab, lamtab,
+                                      0);
             ++napp;
         }
     };
@@ -1013,8 +1032,8 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                     ++total;
                     if (!(rr > target)) break;
                     double zacc = 0.0;
-                    dst256_apply(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), X, Stab, lamtab,
-                                 true, &zacc);
+                    zacc = dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), Stab,
+                                               lamtab, 1);
                     ++napp;
                     const double rzn = block_sum<NW>(zacc, red1);
                     const T beta = (T)(rzn / rz);
@@ -1099,9 +1118,9 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
 template <bool ADJ>
 __global__ __launch_bounds__(1024) void cg_global_dst256(SolveArgs a, const __bf16* __restrict__ Stab,
                                                          const float* __restrict__ lamtab) {
-    __shared__ __align__(16) __bf16 X[256 * D256_LD];
     __shared__ SolveShared sh;
-    cg_global_body<float, ADJ, true>(a, blockIdx.x, 256, a.obs, sh, X, Stab, lamtab);
+    cg_global_body<float, ADJ, true>(a, blockIdx.x, 256, a.obs, sh, reinterpret_cast<__bf16*>(g_mixed_smem), Stab,
+                                     lamtab);
 }
 
 // 1D: the tridiagonal flux-form system has the closed-form solution
@@ -1206,9 +1225,6 @@ bool mixed_supported(int n) { return n == 64 || n == 128 || n == 256; }
 // Each grid's body as a separate function, so that each is register-allocated on its own (the
 // call happens once per particle).  The LDS they share is named directly, not passed by pointer,
 // so that the bodies keep their LDS instructions.
-constexpr int MIXED_SMEM = cmax(onchip_smem<float, 128, 16, true>(),
-                                cmax(onchip_smem<float, 64, 4, true>(), onchip_smem<double, 64, 4, false>()));
-__shared__ __align__(16) unsigned char g_mixed_smem[MIXED_SMEM];
 __shared__ SolveShared g_mixed_sh;
 
 template <typename T, int NN, int R, bool DST>
@@ -1223,7 +1239,6 @@ __device__ __noinline__ void mixed_global(const SolveArgs& a, int64_t p, int n, 
     cg_global_body<T, false>(a, p, n, obs, g_mixed_sh);
 }
 
-static_assert(D256_BYTES <= MIXED_SMEM, "mixed-grid LDS");
 __device__ __noinline__ void mixed_global_dst256(const SolveArgs& a, int64_t p, const int32_t* obs, const __bf16* S,
                                                  const float* lam) {
     cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<__bf16*>(g_mixed_smem), S, lam);
