@@ -22,52 +22,60 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
     const int np1 = n + 1;
     const int npad = (np1 + 15) & ~15;
     constexpr int LD = KLP + 1;                 // padded row stride: conflict-free column reads
+    constexpr int KS = KLP / 4;                 // MFMA steps over the 32 modes of an axis
     double* X = smem;                           // [KLP][LD]
-    double* Bs = X + KLP * LD;                  // [npad][LD]
-    double* T = Bs + npad * LD;                 // [KLP][npad]
+    double* T = X + KLP * LD;                   // [KLP][npad]
 
     for (int t = threadIdx.x; t < KLP * KLP; t += 256) {
         const int k = t / KLP, l = t % KLP;
         X[k * LD + l] = (k < kl && l < kl) ? sqrt_lam[k * kl + l] * xp[k * kl + l] : 0.0;
-    }
-    for (int t = threadIdx.x; t < npad * KLP; t += 256) {
-        const int i = t / KLP, k = t % KLP;
-        Bs[i * LD + k] = (i < np1) ? basis[i * KLP + k] : 0.0;
     }
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int ntj = npad / 16;
-    // T[k][j] = sum_l X[k][l] B[j][l]
-    for (int tile = wave; tile < 2 * ntj; tile += 4) {
-        const int k0 = (tile & 1) * 16, j0 = (tile >> 1) * 16;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // B operand of the 16 grid nodes r0 .. r0+15, straight from the (cache-resident) basis table:
+    // b[s] = B[r0 + lr][4 s + lk], zero past the last node (rows clamped, zeros selected after)
+    auto bfrag = [&](int r0, double (&b)[KS]) {
+        const int r = r0 + lr, rc = r < np1 ? r : np1 - 1;
 #pragma unroll
-        for (int l0 = 0; l0 < KLP; l0 += 4) {
-            const double a = X[(k0 + lr) * LD + l0 + lk];
-            const double b = Bs[(j0 + lr) * LD + l0 + lk];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int s2 = 0; s2 < KS; ++s2) {
+            const double v = basis[rc * KLP + 4 * s2 + lk];
+            b[s2] = r < np1 ? v : 0.0;
         }
+    };
+    // T[k][j] = sum_l X[k][l] B[j][l]; a wave takes node blocks jb = wave, wave + 4, ...
+    for (int jb = wave; jb < ntj; jb += 4) {
+        double b[KS];
+        bfrag(16 * jb, b);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[(k0 + lk + 4 * v) * npad + j0 + lr] = acc[v];
+        for (int k0 = 0; k0 < KLP; k0 += 16) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[(k0 + lr) * LD + 4 * s2 + lk], b[s2], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[(k0 + lk + 4 * v) * npad + 16 * jb + lr] = acc[v];
+        }
     }
     __syncthreads();
-    // U[j][i] = sum_k T[k][j] B[i][k]
-    for (int tile = wave; tile < ntj * ntj; tile += 4) {
-        const int j0 = (tile / ntj) * 16, i0 = (tile % ntj) * 16;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // U[j][i] = sum_k T[k][j] B[i][k]; a wave keeps the B operand of its column block ib and
+    // sweeps the row blocks
+    for (int ib = wave; ib < ntj; ib += 4) {
+        double b[KS];
+        bfrag(16 * ib, b);
+        const int i = 16 * ib + lr;
+        for (int jb = 0; jb < ntj; ++jb) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k0 = 0; k0 < KLP; k0 += 4) {
-            const double a = T[(k0 + lk) * npad + j0 + lr];
-            const double b = Bs[(i0 + lr) * LD + k0 + lk];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-        const int i = i0 + lr;
+            for (int s2 = 0; s2 < KS; ++s2)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[(4 * s2 + lk) * npad + 16 * jb + lr], b[s2], acc, 0, 0, 0);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = j0 + lk + 4 * v;
-            if (i < np1 && j < np1) op[j * np1 + i] = EXPHALF ? exp(0.5 * acc[v]) : acc[v];
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * jb + lk + 4 * v;
+                if (i < np1 && j < np1) op[j * np1 + i] = EXPHALF ? exp(0.5 * acc[v]) : acc[v];
+            }
         }
     }
 }
@@ -210,7 +218,7 @@ hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_la
                           double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     const int npad = (n + 1 + 15) & ~15;
-    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)npad * (KLP + 1) + (size_t)KLP * npad);
+    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
     if (exp_half)
         synth2d_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
     else
@@ -225,7 +233,7 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
     int nmax = 0;
     for (int l = 0; l < lt.n_levels; ++l) nmax = lt.n[l] > nmax ? lt.n[l] : nmax;
     const int npad = (nmax + 1 + 15) & ~15;
-    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)npad * (KLP + 1) + (size_t)KLP * npad);
+    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
     if (exp_half)
         synth2d_levels_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
                                                                              out_stride);
@@ -239,7 +247,7 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
 // that no launch needs an attribute call (launches may be captured into graphs).
 hipError_t prepare_kernels() {
     constexpr int npad = (256 + 1 + 15) & ~15, ipad = (256 + 1 + 3) & ~3;
-    const int synth = (int)sizeof(double) * (KLP * (KLP + 1) + npad * (KLP + 1) + KLP * npad);
+    const int synth = (int)sizeof(double) * (KLP * (KLP + 1) + KLP * npad);
     const int grad = (int)sizeof(double) * (32 * (ipad + 1) + 32 * (KLP + 1));
     const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
     hipError_t e = hipSuccess;
