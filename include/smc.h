@@ -292,8 +292,9 @@ int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M, int32_t it
                smc_stream stream);
 
 /* Re-weighting and next temperature (Alg. 1; App. C): with tau = *tau_in (device scalar),
- * choose h in (0, 1 - tau] by 64 bisection steps keeping ESS(h) >= ess_frac * N, where
- * ESS = 1 / sum W^2 and W_n ∝ exp(-h Phi_n); take h = 1 - tau when that already passes.
+ * choose h in (0, 1 - tau] with ESS(h) = ess_frac * N, where ESS = 1 / sum W^2 and
+ * W_n ∝ exp(-h Phi_n): the largest h (to a relative 2^-52, or (1 - tau) 2^-64) whose ESS still
+ * passes, found by safeguarded Newton steps on log ESS; take h = 1 - tau when that already passes.
  * Outputs (device): *h, *tau_new (= 1 exactly on the last stage), W[N] normalised weights,
  * *log_z_inc = log((1/N) sum exp(-h Phi)).  Non-finite Phi get weight 0.  A zero step sets
  * SMC_FLAG_STALL and no finite potential sets SMC_FLAG_NONFINITE in *flags (device, may be

@@ -19,38 +19,91 @@ __device__ __forceinline__ double block_max_all(double v, double* red) {
     return m;
 }
 
-// ESS(h) = (sum W)^2 / sum W^2 with W_n = exp(-h (Phi_n - Phi_min)); non-finite Phi weigh 0.
-// Returns log S1 (into *ls1) and log ESS.
-__device__ double log_ess(const double* phi, int64_t N, double pmin, double h, double* ls1, double* red1,
-                          double* red2) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t k = threadIdx.x; k < N; k += TB) {
-        const double p = phi[k];
-        if (isfinite(p)) {
-            const double w = exp(-h * (p - pmin));
-            s1 += w;
-            s2 += w * w;
+// ESS(h) = (sum W)^2 / sum W^2 with W_n = exp(-h d_n), d_n = Phi_n - Phi_min; non-finite Phi weigh 0.
+// One pass gives S1 = sum W, S2 = sum W^2, D1 = sum d W, D2 = sum d W^2 and Q = sum d^2 W, so that
+//   f(h) = log ESS(h) - log(rho N) = 2 log S1 - log S2 - log(rho N),
+//   f'(h) = -2 D1 / S1 + 2 D2 / S2,
+// and at h = 0, Q / S1 - (D1 / S1)^2 is the variance of d.  Thread t takes particles t, t + TB, ...;
+// their d sit in registers when N <= TCACHE TB, and the sums run in the same order either way.
+constexpr int TCACHE = 8;
+
+struct EssSums {
+    double s1, s2, d1, d2, q;
+};
+
+__device__ EssSums ess_sums(const double* __restrict__ phi, int64_t N, double pmin, double h,
+                            const double (&dc)[TCACHE], bool cached, double (*red)[5]) {
+    double s1 = 0.0, s2 = 0.0, d1 = 0.0, d2 = 0.0, q = 0.0;
+    auto add = [&](double d) {
+        const double w = exp(-h * d), ww = w * w;
+        s1 += w;
+        s2 += ww;
+        d1 += d * w;
+        d2 += d * ww;
+        q += d * d * w;
+    };
+    if (cached) {
+#pragma unroll
+        for (int i = 0; i < TCACHE; ++i)
+            if (dc[i] >= 0.0) add(dc[i]);
+    } else {
+        for (int64_t k = threadIdx.x; k < N; k += TB) {
+            const double p = phi[k];
+            if (isfinite(p)) add(p - pmin);
         }
     }
-    const double S1 = block_sum<TW>(s1, red1);
-    const double S2 = block_sum<TW>(s2, red2);
-    __syncthreads();   // red1/red2 are reused by the next call
-    *ls1 = log(S1);
-    return 2.0 * log(S1) - log(S2);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    d1 = wave_sum(d1);
+    d2 = wave_sum(d2);
+    q = wave_sum(q);
+    if ((threadIdx.x & 63) == 0) {
+        double* r = red[threadIdx.x >> 6];
+        r[0] = s1;
+        r[1] = s2;
+        r[2] = d1;
+        r[3] = d2;
+        r[4] = q;
+    }
+    __syncthreads();
+    EssSums o{0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int w = 0; w < TW; ++w) {
+        o.s1 += red[w][0];
+        o.s2 += red[w][1];
+        o.d1 += red[w][2];
+        o.d2 += red[w][3];
+        o.q += red[w][4];
+    }
+    __syncthreads();   // red is reused by the next pass
+    o.s1 = uniform(o.s1);
+    o.s2 = uniform(o.s2);
+    o.d1 = uniform(o.d1);
+    o.d2 = uniform(o.d2);
+    o.q = uniform(o.q);
+    return o;
 }
 
+// Next increment h in (0, 1 - tau]: the whole remaining step if its ESS passes, else the root of
+// the decreasing f, kept in a bracket [lo, hi] with f(lo) >= 0 > f(hi).  The first point is the
+// root of the expansion f(h) ~ f(0) - h^2 Var(d); then Newton steps in log h (ESS falls off like a
+// power of h for spread-out potentials), replaced by the bracket's geometric (or arithmetic) mean
+// whenever a step would leave the bracket, until the bracket is 2^-52 relative or the bisection
+// resolution (1 - tau) 2^-64 wide.  The returned h always has f(h) >= 0, ESS >= rho N, as the lower
+// end of a bisection would; about 10 passes replace 66.  Every thread holds the same sums, so
+// every branch below is uniform.
 __global__ __launch_bounds__(TB) void temper_kernel(int64_t N, const double* __restrict__ phi,
                                                     const double* __restrict__ tau_in, double ess_frac,
                                                     double* __restrict__ h_out, double* __restrict__ tau_out,
                                                     double* __restrict__ W, double* __restrict__ log_z,
                                                     int32_t* __restrict__ flags) {
-    __shared__ double red1[TW], red2[TW];
+    __shared__ double red[TW][5];
     double pmin = INFINITY;
     for (int64_t k = threadIdx.x; k < N; k += TB) {
         const double p = phi[k];
         if (isfinite(p)) pmin = fmin(pmin, p);
     }
-    pmin = -block_max_all(-pmin, red1);
+    pmin = uniform(-block_max_all(-pmin, &red[0][0]));
     const double tau = *tau_in;
     const double rest = 1.0 - tau;
     if (!isfinite(pmin)) {   // no finite potential: nothing to weigh
@@ -63,23 +116,49 @@ __global__ __launch_bounds__(TB) void temper_kernel(int64_t N, const double* __r
         }
         return;
     }
+    const bool cached = N <= (int64_t)TCACHE * TB;
+    double dc[TCACHE];
+#pragma unroll
+    for (int i = 0; i < TCACHE; ++i) {
+        const int64_t k = threadIdx.x + (int64_t)i * TB;
+        const double p = (cached && k < N) ? phi[k] : NAN;
+        dc[i] = isfinite(p) ? p - pmin : -1.0;
+    }
     const double target = log(ess_frac * (double)N);
-    double ls1;
+    auto f_of = [&](const EssSums& e) { return 2.0 * log(e.s1) - log(e.s2) - target; };
     double h;
     bool last = false;
-    if (log_ess(phi, N, pmin, rest, &ls1, red1, red2) >= target) {
+    EssSums e = ess_sums(phi, N, pmin, rest, dc, cached, red);
+    if (f_of(e) >= 0.0) {
         h = rest;
         last = true;
     } else {
         double lo = 0.0, hi = rest;
-        for (int it = 0; it < 64; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (log_ess(phi, N, pmin, mid, &ls1, red1, red2) >= target) lo = mid;
-            else hi = mid;
+        const double floor_w = rest * 0x1p-64;
+        const EssSums e0 = ess_sums(phi, N, pmin, 0.0, dc, cached, red);
+        const double f0 = f_of(e0), m = e0.d1 / e0.s1, v = e0.q / e0.s1 - m * m;
+        double x = (v > 0.0 && f0 > 0.0) ? fmin(sqrt(f0 / v), 0.5 * rest) : 0.5 * rest;
+        for (int it = 0; it < 96; ++it) {
+            e = ess_sums(phi, N, pmin, x, dc, cached, red);
+            const double fx = f_of(e);
+            const bool pass = fx >= 0.0;
+            if (pass) lo = x;
+            else hi = x;
+            if (!(hi - lo > fmax(floor_w, hi * 0x1p-52))) break;
+            const double dfx = -2.0 * e.d1 / e.s1 + 2.0 * e.d2 / e.s2;
+            const double step = -fx / (dfx * x);   // Newton in s = log h
+            double xn = (fabs(step) < 50.0) ? x * exp(step) : NAN;
+            if (!(xn > lo && xn < hi)) xn = lo > 0.0 ? sqrt(lo * hi) : 0.5 * (lo + hi);
+            if (fabs(xn - x) <= fmax(floor_w, xn * 0x1p-52)) {   // converged next to the root
+                if (pass) break;
+                xn = fmax(lo, x * (1.0 - 0x1p-46));           // the root lies just below x
+            }
+            x = xn;
         }
         h = lo;
     }
-    log_ess(phi, N, pmin, h, &ls1, red1, red2);   // normaliser at the chosen h
+    e = ess_sums(phi, N, pmin, h, dc, cached, red);   // normaliser at the chosen h
+    const double ls1 = log(e.s1);
     for (int64_t k = threadIdx.x; k < N; k += TB) {
         const double p = phi[k];
         W[k] = isfinite(p) ? exp(-h * (p - pmin) - ls1) : 0.0;
