@@ -49,6 +49,11 @@ typedef enum {
 #define SMC_FLAG_BADLEVEL 16   /* a level map named a grid the problem does not have */
 #define SMC_FLAG_BADPARAM 32   /* a device-side beta or tau was out of range (moves rejected) */
 
+/* Level-map value that parks a particle: it is not solved and not moved (see smc_forward_batch
+ * and smc_gmpcn_stage), and it sets no flag.  A sampler whose temperature has reached 1 parks
+ * its particles while the samplers sharing its launch go on. */
+#define SMC_LEVEL_PARKED (-1)
+
 typedef enum {
     SMC_FP64 = 0,        /* conjugate gradients in FP64 */
     SMC_FP32_REFINE = 1  /* FP32 conjugate gradients inside FP64 residual refinement */
@@ -159,7 +164,8 @@ int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, do
  *   level  [N] device, grid index per particle, or NULL for grid 0.  With a level map all
  *          particles run in one persistent launch (2D, grids of 64, 128 and 256 intervals);
  *          a particle whose level is out of range gets G = NaN, iters = -1 and sets
- *          SMC_FLAG_BADLEVEL
+ *          SMC_FLAG_BADLEVEL; level SMC_LEVEL_PARKED gives the same outputs without a solve
+ *          and without the flag
  *   prec   smc_precision (1D problems always solve directly in FP64)
  *   G      [N][n_obs] out; NaN rows for solves that did not converge
  *   iters  [N] out, conjugate-gradient iterations, -1 when not converged; may be NULL */
@@ -209,7 +215,9 @@ typedef struct {
 
 /* n_moves pCN-GM steps as smc_gmpcn_move, with each particle's beta, tau and mixture taken
  * from its group in `st`, read on the device when the kernels run.  Particles of a group with
- * beta outside (0, 1] or tau outside [0, 1] keep their state and set SMC_FLAG_BADPARAM. */
+ * beta outside (0, 1] or tau outside [0, 1] keep their state and set SMC_FLAG_BADPARAM.
+ * Particles whose level is SMC_LEVEL_PARKED (read when the kernels run, so a captured stage
+ * follows changes to the map) keep xi and phi, get n_acc = 0 and cost no solve. */
 int smc_gmpcn_stage(smc_problem p, int64_t N, const int32_t* level, const smc_stage* st, int32_t n_moves,
                     int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
 

@@ -50,13 +50,18 @@ def adapt_beta(beta, rate):
     return beta
 
 
-def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stages=500):
-    """Returns dict(xi, phi, taus, log_Z, betas, rates)."""
+def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stages=500, xi0=None, ids=None,
+        ctr_off=0):
+    """Returns dict(xi, phi, taus, log_Z, betas, rates).
+
+    A sampler that shares its random streams with others (several samplers in one batch) passes
+    its starting cloud xi0, its particles' ids (the words of their streams) and ctr_off, added to
+    the counter of its resampling uniform and its mixture seeding."""
     from .forward import phi as phi_pde
     K = prob.K
     f = phi_fn if phi_fn is not None else (lambda x: phi_pde(prob, x, n))
     active = prob.active() if kr is None else np.arange(kr)
-    xi = prior_sample(K, N, seed, 0)
+    xi = prior_sample(K, N, seed, 0) if xi0 is None else np.array(xi0, dtype=np.float64)
     phi = np.array([f(x) for x in xi])
     tau, beta, log_Z = 0.0, float(beta0), 0.0
     taus, betas, rates = [0.0], [], []
@@ -66,15 +71,15 @@ def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stag
             raise RuntimeError("temperature bisection stalled")
         log_Z += lz
         taus.append(tau)
-        idx = systematic(W, resample_u53(seed, s * STAGE_STRIDE))
+        idx = systematic(W, resample_u53(seed, s * STAGE_STRIDE + ctr_off))
         xi, phi = xi[idx], phi[idx]
         if M == 1:
             gm = pcn_gm(K, active)
         else:
-            logw, mean, var, _ = gmfit.fit_philox(xi[:, active], M, seed, s * STAGE_STRIDE)
+            logw, mean, var, _ = gmfit.fit_philox(xi[:, active], M, seed, s * STAGE_STRIDE + ctr_off)
             gm = GM(logw, mean, var, active, K)
         xi, phi, n_acc = gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
-                                     phi_fn=f)
+                                     phi_fn=f, ids=ids)
         rate = n_acc.sum() / (N * n_moves)
         betas.append(beta)
         rates.append(rate)

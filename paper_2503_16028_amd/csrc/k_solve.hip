@@ -1195,6 +1195,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __
             if (p < N) {
                 const int l = level[p];
                 f = (target >= 0) ? (l == target) : (l < 0 || l >= lt.n_levels);
+                // level -1 parks a particle: listed with the out-of-range ones (no solve) but no error
+                bad = bad || (target < 0 && l != -1 && f);
             }
             const unsigned long long m = __ballot(f);
             const int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -1207,11 +1209,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __
             }
             if (f) list[base + off + before] = (int32_t)p;
             base += tot;
-            bad = bad || (target < 0 && tot > 0);
             __syncthreads();
         }
     }
-    if (tid == 0 && bad && flags) atomicOr(flags, SMC_FLAG_BADLEVEL);
+    if (__syncthreads_or(bad) && tid == 0 && flags) atomicOr(flags, SMC_FLAG_BADLEVEL);
 }
 
 hipError_t launch_plan(int64_t N, const int32_t* level, const LevelTable& lt, int32_t* list,

@@ -14,6 +14,8 @@ host reads back the temperature (and the acceptance count) once per stage.  Rand
 stage s draws its resampling uniform from Philox block 0x80000001 and its moves, mixture fit and
 mixture draws at counters s * 2^20 (+ move index), so a run is a function of its seed alone.
 """
+import math
+
 import torch
 
 from . import smc
@@ -137,3 +139,136 @@ class SMCGMSampler(SMCSampler):
         self.log_Z += float(self.log_z.item())
         self.history.append(dict(stage=self.stage, tau=tau, h=float(self.h.item())))
         return tau
+
+
+class MixedSampler:
+    """Independent SMC-pCN-GM samplers on the grids of one problem, moved together.
+
+    Sampler g owns the particles [off_g, off_g + N_g) and solves on grid g; it has its own
+    temperature, increment, step size, resampling, mixture and evidence, exactly as SMCSampler
+    would run it on that grid alone.  Each stage, every sampler still below temperature 1
+    re-weights, resamples and fits its mixture on its own rows; then one smc_gmpcn_stage (captured
+    once as a HIP graph) moves all of them, one persistent launch per move serving the three grids
+    at once.  A sampler whose temperature reaches 1 parks its particles (level SMC_LEVEL_PARKED):
+    its final cloud is kept as it is and costs nothing in later stages.
+
+    Random numbers: moves at counter s * 2^20 + m, with a particle's global index as its word, so
+    sampler 0 draws exactly what SMCSampler draws with N_0 particles; sampler g takes its
+    resampling uniform and mixture seeding at counter s * 2^20 + g.
+    """
+
+    def __init__(self, problem, counts, M, n_moves, ess_frac=0.5, beta0=0.2, prec=smc.SMC_FP32_REFINE, seed=0,
+                 device="cuda", fit_iters=50, graph=True):
+        G = len(counts)
+        if G != len(problem.grids):
+            raise ValueError("one sampler per grid of the problem (%d), got %d" % (len(problem.grids), G))
+        if M < 2:
+            raise ValueError("MixedSampler fits a mixture of M >= 2 components")
+        self.p, self.counts, self.M, self.n_moves = problem, [int(c) for c in counts], int(M), int(n_moves)
+        self.N = sum(self.counts)
+        self.offs = [sum(self.counts[:g]) for g in range(G)]
+        self.ess_frac, self.prec, self.seed, self.fit_iters = ess_frac, prec, int(seed), int(fit_iters)
+        self.betas = [float(beta0)] * G
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        N, K, kr = self.N, problem.K, problem.kr
+        self.stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(self.stream):
+            self.xi = torch.empty(N, K, **f64)
+            self.xi2 = torch.empty(N, K, **f64)
+            self.phi = torch.empty(N, **f64)
+            self.phi2 = torch.empty(N, **f64)
+            self.W = torch.empty(N, **f64)
+            self.idx = torch.empty(N, dtype=torch.int32, device=dev)
+            self.n_acc = torch.zeros(N, dtype=torch.int32, device=dev)
+            self.level = torch.cat([torch.full((c,), g, dtype=torch.int32) for g, c in enumerate(self.counts)]).to(dev)
+            self.home = self.level.clone()
+            self.flags = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.tau = torch.zeros(G, **f64)
+            self.tau_new = torch.zeros(G, **f64)
+            self.h = torch.zeros(G, **f64)
+            self.log_z = torch.zeros(G, **f64)
+            self.logw = torch.full((G, M), -math.log(M), **f64)
+            self.mean = torch.zeros(G, M, kr, **f64)
+            self.scale = torch.ones(G, M, kr, **f64)
+            self.beta = torch.tensor(self.betas, **f64)
+            self.ctr = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.sd = smc.stage_desc(G, self.logw, self.mean, self.scale, self.beta, self.tau, self.ctr, self.seed)
+        self.stream.synchronize()
+        self.graph = None
+        if graph:
+            self.graph = smc.StageGraph(problem, N, self.level, self.sd, self.n_moves, prec, self.xi, self.phi,
+                                        self.n_acc, self.stream)
+        self.stage = 0
+        self.running = list(range(G))
+        self.log_Z = [0.0] * G
+        self.history = [[] for _ in range(G)]
+
+    def rows(self, g):
+        return slice(self.offs[g], self.offs[g] + self.counts[g])
+
+    def initialise(self):
+        with torch.cuda.stream(self.stream):
+            smc.smc_prior_sample(self.p, self.N, self.seed, 0, self.xi)
+            smc.smc_phi_batch(self.p, self.N, self.xi, self.level, self.prec, self.phi)
+
+    def step(self):
+        """One stage of every running sampler: temper, resample, gather, fit; then one move stage."""
+        p, K = self.p, self.p.K
+        self.stage += 1
+        base = self.stage * STAGE_STRIDE
+        with torch.cuda.stream(self.stream):
+            for g in self.running:
+                r, n = self.rows(g), self.counts[g]
+                one = slice(g, g + 1)
+                smc.smc_temper(n, self.phi[r], self.tau[one], self.ess_frac, self.h[one], self.tau_new[one], self.W[r],
+                               self.log_z[one], self.flags)
+                smc.smc_resample(n, self.W[r], smc.smc_philox_u53(self.seed, base + g), self.idx[r], self.flags)
+                smc.smc_gather(n, K, self.idx[r], self.xi[r], self.phi[r], self.xi2[r], self.phi2[r])
+                self.xi[r].copy_(self.xi2[r])            # the captured stage reads xi and phi in place
+                self.phi[r].copy_(self.phi2[r])
+                self.tau[one].copy_(self.tau_new[one])
+                smc.smc_gm_fit(p, n, self.xi[r], self.M, self.fit_iters, 1e-3, self.seed, base + g, self.logw[g],
+                               self.mean[g], self.scale[g])
+            self.beta.copy_(torch.tensor(self.betas, dtype=torch.float64))
+            self.ctr.fill_(base)
+            if self.graph is not None:
+                self.graph.launch(self.stream)
+            else:
+                smc.smc_gmpcn_stage(p, self.N, self.level, self.sd, self.n_moves, self.prec, self.xi, self.phi,
+                                    self.n_acc)
+            acc = self.n_acc.cpu().numpy()
+            taus = self.tau.cpu().numpy()
+            hs = self.h.cpu().numpy()
+            lzs = self.log_z.cpu().numpy()
+            for g in list(self.running):
+                r = self.rows(g)
+                rate = float(acc[r].sum()) / (self.counts[g] * max(1, self.n_moves))
+                self.log_Z[g] += float(lzs[g])
+                self.history[g].append(dict(stage=self.stage, tau=float(taus[g]), h=float(hs[g]), beta=self.betas[g],
+                                            rate=rate))
+                if rate > 0.3:
+                    self.betas[g] = min(1.0, 2.0 * self.betas[g])
+                elif rate < 0.15:
+                    self.betas[g] *= 0.5
+                if taus[g] >= 1.0:
+                    self.level[r].fill_(smc.LEVEL_PARKED)
+                    self.running.remove(g)
+            self.stream.synchronize()
+        return len(self.running)
+
+    def run(self, max_stages=500):
+        self.initialise()
+        for _ in range(max_stages):
+            if self.step() == 0:
+                break
+        self.stream.synchronize()
+        if int(self.flags.item()) & smc.FLAG_STALL:
+            raise RuntimeError("temperature bisection stalled")
+        return [dict(xi=self.xi[self.rows(g)], phi=self.phi[self.rows(g)], log_Z=self.log_Z[g],
+                     history=self.history[g]) for g in range(len(self.counts))]
+
+    def close(self):
+        if self.graph is not None:
+            self.graph.close()
+            self.graph = None

@@ -17,6 +17,7 @@ SMC_OK = 0
 SMC_FP64 = 0
 SMC_FP32_REFINE = 1
 FLAG_NOCONV, FLAG_STALL, FLAG_NONFINITE, FLAG_BADWEIGHTS, FLAG_BADLEVEL, FLAG_BADPARAM = 1, 2, 4, 8, 16, 32
+LEVEL_PARKED = -1
 PRECISIONS = {"fp64": SMC_FP64, "fp32_refine": SMC_FP32_REFINE}
 PRECOND_AUTO, PRECOND_JACOBI = 0, 1
 

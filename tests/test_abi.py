@@ -117,3 +117,17 @@ def test_host_philox_matches_the_oracle_generator(libsmc):
             assert smc.smc_philox_u53(seed, ctr, gmfit.KMPP_BLOCK, m) == gmfit.kmpp_u53(seed, ctr, m)
         w = philox.philox4x32_10([5, 9, ctr & philox.MASK32, ctr >> 32], philox._key(seed))
         assert smc.smc_philox_u53(seed, ctr, 5, 9) == (int(w[0]) >> 5) * (1 << 26) + (int(w[1]) >> 6)
+
+
+def test_binding_constants_match_the_header():
+    """Status codes, precisions, flag bits and the parked level of the binding are the header's."""
+    from paper_2503_16028_amd import smc
+    text = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SMC_(\w+) \(?(-?\d+)\)?", text)}
+    for name in ("NOCONV", "STALL", "NONFINITE", "BADWEIGHTS", "BADLEVEL", "BADPARAM"):
+        assert getattr(smc, "FLAG_" + name) == defs["FLAG_" + name], name
+    assert smc.LEVEL_PARKED == defs["LEVEL_PARKED"]
+    enums = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(SMC_\w+)\s*=\s*(-?\d+)", text)}
+    assert smc.SMC_OK == enums["SMC_OK"]
+    assert smc.SMC_FP64 == enums["SMC_FP64"] and smc.SMC_FP32_REFINE == enums["SMC_FP32_REFINE"]
+    assert smc.PRECOND_AUTO == defs["PRECOND_AUTO"] and smc.PRECOND_JACOBI == defs["PRECOND_JACOBI"]

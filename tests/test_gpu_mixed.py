@@ -253,3 +253,124 @@ def test_stage_graph_replays_match_eager():
         graph.close()
     assert total > 0
     assert smc.smc_status_flags(p) == 0
+
+
+def test_levels_converge_second_order():
+    """The same xi on the three nested grids in one launch: successive differences of G and Phi
+    shrink by four per halving of h, with the ratios the oracle's direct solves give."""
+    from paper_2503_16028_amd import smc
+    banner("levels converge second order")
+    d, op = load("c5")
+    xi1 = inputs.particles(2, op.K, 49)
+    xi = np.repeat(xi1, 3, axis=0)
+    lv = np.tile(np.arange(3, dtype=np.int32), 2)
+    N = len(lv)
+    p = mixed_problem(d, N, "fp32_refine")
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), t(lv, torch.int32), smc.SMC_FP32_REFINE, G)
+    smc.smc_potential(p, N, G, phi)
+    torch.cuda.synchronize()
+    g, ph = G.cpu().numpy().reshape(2, 3, -1), phi.cpu().numpy().reshape(2, 3)
+    for k in range(2):
+        r = np.linalg.norm(g[k, 0] - g[k, 1]) / np.linalg.norm(g[k, 1] - g[k, 2])
+        rp = (ph[k, 0] - ph[k, 1]) / (ph[k, 1] - ph[k, 2])
+        ref = [observe(op, solve(op, synthesize(op, xi1[k], n), n), n) for n in GRIDS]
+        rr = np.linalg.norm(ref[0] - ref[1]) / np.linalg.norm(ref[1] - ref[2])
+        assert 3.8 < r < 4.2 and 3.8 < rp < 4.2, (k, r, rp)
+        assert abs(r / rr - 1) < 1e-3, (k, r, rr)
+
+
+def test_parked_particles_keep_their_state():
+    """Level SMC_LEVEL_PARKED: a forward call gives NaN rows and iters = -1 without a flag; a stage
+    leaves parked particles as they are (n_acc = 0) and gives every other particle the bits it
+    gets when nothing is parked."""
+    from paper_2503_16028_amd import smc
+    banner("parked particles")
+    d, op = load("c5")
+    home = np.array([0, 1, 2, 0, 1, 0, 2, 1], dtype=np.int32)
+    parked = home.copy()
+    parked[[1, 2, 5]] = smc.LEVEL_PARKED
+    N, M, n_moves = len(home), 2, 2
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 50) * 0.3
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_status_flags(p)
+    smc.smc_forward_batch(p, N, t(xi), t(parked, torch.int32), smc.SMC_FP32_REFINE, G, it)
+    torch.cuda.synchronize()
+    g, i = G.cpu().numpy(), it.cpu().numpy()
+    assert smc.smc_status_flags(p) == 0
+    assert np.isnan(g[[1, 2, 5]]).all() and (i[[1, 2, 5]] == -1).all()
+    assert np.isfinite(g[parked >= 0]).all() and (i[parked >= 0] > 0).all()
+    phi0 = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), t(home, torch.int32), smc.SMC_FP32_REFINE, G)
+    smc.smc_potential(p, N, G, phi0)
+    logw, mean, scale = group_mixture(op, 3, M, 51)
+    sd = smc.stage_desc(3, t(logw), t(mean), t(scale), t([0.3, 0.3, 0.3]), t([1e-3, 1e-3, 1e-3]),
+                        torch.tensor([900], dtype=torch.int64, device=DEV), 13)
+    out = []
+    for lv in (home, parked):
+        X, P, A = t(xi), phi0.clone(), torch.empty(N, dtype=torch.int32, device=DEV)
+        smc.smc_gmpcn_stage(p, N, t(lv, torch.int32), sd, n_moves, smc.SMC_FP32_REFINE, X, P, A)
+        torch.cuda.synchronize()
+        out.append((X.cpu().numpy(), P.cpu().numpy(), A.cpu().numpy()))
+    assert smc.smc_status_flags(p) == 0
+    (xh, ph, ah), (xp, pp, ap) = out
+    keep = parked >= 0
+    assert np.array_equal(xh[keep], xp[keep]) and np.array_equal(ph[keep], pp[keep]) and np.array_equal(ah[keep], ap[keep])
+    assert np.array_equal(xp[~keep], xi[~keep]) and np.array_equal(pp[~keep], phi0.cpu().numpy()[~keep])
+    assert (ap[~keep] == 0).all() and ah[~keep].sum() > 0 and ah[keep].sum() > 0
+
+
+def test_mixed_sampler_replays_the_oracle_runs():
+    """Three samplers on 64^2, 128^2 and 256^2 run to temperature 1 by MixedSampler: the 64^2 and
+    128^2 samplers replay the oracle's runs on their grids from the same seed (the same
+    temperatures, step sizes, accept rates, log Z and final clouds); every sampler reaches 1 and
+    keeps its cloud from then on; the captured and the eager stage give the same bits."""
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import MixedSampler
+    from oracle import smc as osmc
+    from oracle.moves import prior_sample
+    banner("mixed sampler replay fp64")
+    d, op = load("c5")
+    counts, M, n_moves, seed = (32, 8, 4), 4, 2, 5
+    N = sum(counts)
+    p = mixed_problem(d, N, "fp64")
+    runs = []
+    for graph in (True, False):
+        ms = MixedSampler(p, counts, M, n_moves, prec=smc.SMC_FP64, seed=seed, graph=graph)
+        ms.initialise()
+        frozen = {}
+        for _ in range(200):
+            before = list(ms.running)
+            left = ms.step()
+            for g in before:
+                if g not in ms.running:
+                    r = ms.rows(g)
+                    frozen[g] = (ms.xi[r].cpu().numpy().copy(), ms.phi[r].cpu().numpy().copy())
+            if left == 0:
+                break
+        res = [dict(xi=ms.xi[ms.rows(g)].cpu().numpy(), phi=ms.phi[ms.rows(g)].cpu().numpy(), log_Z=ms.log_Z[g],
+                    history=ms.history[g]) for g in range(3)]
+        ms.close()
+        assert smc.smc_status_flags(p) == 0 and int(ms.flags.item()) == 0
+        for g in range(3):
+            assert res[g]["history"][-1]["tau"] == 1.0
+            assert np.array_equal(res[g]["xi"], frozen[g][0]) and np.array_equal(res[g]["phi"], frozen[g][1])
+        runs.append(res)
+    for g in range(3):
+        assert np.array_equal(runs[0][g]["xi"], runs[1][g]["xi"]) and runs[0][g]["log_Z"] == runs[1][g]["log_Z"]
+    xi_all = prior_sample(op.K, N, seed, 0)
+    for g in (0, 1):
+        r = slice(sum(counts[:g]), sum(counts[:g + 1]))
+        ids = np.arange(N)[r]
+        ref = osmc.run(op, GRIDS[g], counts[g], M=M, n_moves=n_moves, rho=0.5, beta0=0.2, seed=seed, xi0=xi_all[r],
+                       ids=ids, ctr_off=g)
+        out = runs[0][g]
+        taus = [0.0] + [h["tau"] for h in out["history"]]
+        assert len(taus) == len(ref["taus"]) and np.allclose(taus, ref["taus"], rtol=1e-9, atol=1e-12), g
+        assert [h["beta"] for h in out["history"]] == ref["betas"], g
+        assert np.allclose([h["rate"] for h in out["history"]], ref["rates"], rtol=0, atol=0), g
+        assert out["log_Z"] == pytest.approx(ref["log_Z"], abs=1e-8)
+        assert np.abs(out["xi"] - ref["xi"]).max() <= 1e-7 * np.abs(ref["xi"]).max(), g

@@ -207,3 +207,21 @@ def test_mirror_symmetry_c3(problems):
     # points of equal potential: the posterior has two mirror modes
     assert np.linalg.norm(xt - reflect_x(p, xt)) > 1.0
     assert abs(phi(p, xt, 128) - phi(p, reflect_x(p, xt), 128)) <= 1e-9 * phi(p, xt, 128)
+
+
+def test_nested_grids_converge_second_order(problems):
+    """The three grids of the mixed-resolution runs nest (h = 1/64, 1/128, 1/256), so the same xi
+    gives the same field at every shared node and the observations sit on nodes of each grid.
+    The five-point flux discretisation is second order: successive differences of G and of Phi
+    shrink by four per halving of h (Sec. 3.2 compares the resolutions by this)."""
+    from oracle.forward import phi
+    p = problems["c5"]
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        xi = rng.standard_normal(p.K)
+        G = [forward(p, xi, n) for n in (64, 128, 256)]
+        r = np.linalg.norm(G[0] - G[1]) / np.linalg.norm(G[1] - G[2])
+        ph = [phi(p, xi, n) for n in (64, 128, 256)]
+        rp = (ph[0] - ph[1]) / (ph[1] - ph[2])
+        assert 3.8 < r < 4.2 and 3.8 < rp < 4.2, (r, rp)
+        assert np.linalg.norm(G[1] - G[2]) < 1e-3 * np.linalg.norm(G[2])
