@@ -225,11 +225,11 @@ def test_pcnl_move_fp64(grid, N, beta, n_moves):
     assert np.abs(g.cpu().numpy() - rg).max() <= 1e-7 * np.abs(rg).max()
 
 
-def test_pcnl_move_fp32_refine_c4_sampled():
-    """The C4 workload shape (128^2, pCN-Langevin, FP32+refinement): 2 moves of 256 particles,
+def test_pcnl_move_fp32_refine_128_sampled():
+    """The 128^2 pCN-Langevin workload shape (FP32+refinement): 2 moves of 256 particles,
     three particles replayed by the oracle."""
     from paper_2503_16028_amd import smc
-    banner("pcnl fp32+refine c4 sampled")
+    banner("pcnl fp32+refine 128 sampled")
     d, op = load("c4")
     grid, N, beta, n_moves = 128, 256, 0.2, 2
     p = smc.Problem(d, N, grids=[grid], tol64=1e-10, tol_inner=1e-5)
