@@ -242,6 +242,10 @@ struct SolveShared {
 // call passes them as generic pointers).
 typedef const __attribute__((address_space(1))) double* gcdp;
 typedef __attribute__((address_space(1))) double* gdp;
+// Read-only data through the constant address space: wave-uniform loads of it become scalar loads
+// into SGPRs, which leaves the vector registers to the strip's own loads.  Only for arrays no
+// kernel writes while it runs (the coefficient field, written by the synthesis launch before).
+typedef const __attribute__((address_space(4))) double* kcdp;
 
 // Right-hand side of the pass at interior unknown `flat`: f, or the adjoint's point sources.
 __device__ __forceinline__ double strip_rhs(int flat, bool sources, double f, const double* src_w, const int* src_at,
@@ -280,7 +284,8 @@ __device__ __forceinline__ double from_prev_lane(double v, double edge) {
 // returns the sum of squares of the unscaled residual.  Every load has a clamped, in-bounds index
 // and a select discards what lies outside the domain, so the strip is straight-line code whose
 // loads are issued 8 rows at a time.  The east and west values of e and x come from the adjacent
-// lanes; only the two wave edges load them (e, read-only here, through the scalar unit).
+// lanes; only the two wave edges load them (e, read-only here, through the scalar unit: in SGPRs
+// they leave the vector registers to the rows' loads).
 template <typename T, int NN, int R, bool SRC>
 __device__ __noinline__ double strip_residual(const double* __restrict__ e_, const double* __restrict__ xo_,
                                               const double* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
@@ -313,7 +318,7 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
     const int ieE = min(c0 + 65, NN), ieW = c0;                     // e columns beyond the wave's edges
     const int cxE = min(c0 + 64, NN - 1), cxW = max(c0 - 1, 0);     // x columns beyond the edges
     const bool xEok = c0 + 64 < NN - 1, xWok = c0 > 0;
-    gcdp eu = (gcdp)wave_uniform(e_);
+    kcdp eu = (kcdp)wave_uniform(e_);
     const int g0u = __builtin_amdgcn_readfirstlane(g0);
     double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
     double xS = xo[max(g0 - 1, 0) * NN + c], xC = xo[g0 * NN + c];
@@ -366,7 +371,7 @@ __device__ __noinline__ void strip_update(double* xo_, const double* sd_, const 
     gdp xo = (gdp)xo_;
     gcdp sd = (gcdp)sd_;
     const __attribute__((address_space(3))) T* tb = (const __attribute__((address_space(3))) T*)tb_;
-    constexpr int B = R < 8 ? R : 8;
+    constexpr int B = R < 16 ? R : 16;   // rows whose loads are issued together
 #pragma unroll 1
     for (int r0 = 0; r0 < R; r0 += B) {
         double sdv[B], xv[B];
@@ -398,10 +403,10 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, double* 
     const int lane = threadIdx.x & 63;
     const int c0 = __builtin_amdgcn_readfirstlane(c - lane);
     const int ieE = min(c0 + 65, NN), ieW = c0;
-    gcdp eu = (gcdp)wave_uniform(e_);
+    kcdp eu = (kcdp)wave_uniform(e_);
     const int g0u = __builtin_amdgcn_readfirstlane(g0);
     double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
-    constexpr int B = R < 8 ? R : 8;
+    constexpr int B = R < 16 ? R : 16;
 #pragma unroll 1
     for (int r0 = 0; r0 < R; r0 += B) {
         double eN[B], eEe[B], eWe[B];
