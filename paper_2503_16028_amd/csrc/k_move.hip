@@ -86,7 +86,8 @@ __device__ __forceinline__ int choose_component(uint64_t seed, uint64_t ctr, int
 // a sum over the active modes only (g = gamma).  The first argument of alpha is where the
 // reverse move lands.  This is the ratio of the Gaussian components' Radon-Nikodym
 // derivatives of eq. (auv of pCN-GMM4) written out for diagonal covariances.
-__global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __restrict__ active,
+template <int NT>
+__global__ __launch_bounds__(NT) void propose_kernel(int K, const int32_t* __restrict__ active,
                                                       const int32_t* __restrict__ slot, MoveParams q,
                                                       const double* __restrict__ xi, double* __restrict__ v,
                                                       double* __restrict__ logr, int32_t* flags) {
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __re
     const double* xp = xi + n * K;
     double* vp = v + n * K;
     if (grp < 0 || !mp_valid(beta, tau)) {   // no valid parameters: propose the current state, reject it
-        for (int k = threadIdx.x; k < K; k += 256) vp[k] = xp[k];
+        for (int k = threadIdx.x; k < K; k += NT) vp[k] = xp[k];
         if (threadIdx.x == 0) {
             logr[n] = -INFINITY;
             if (grp >= 0 && flags) atomicOr(flags, SMC_FLAG_BADPARAM);
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __re
     __syncthreads();
     const int j = comp;
     const int nb = (K + 1) / 2;
-    for (int blk = threadIdx.x; blk < nb; blk += 256) {
+    for (int blk = threadIdx.x; blk < nb; blk += NT) {
         double z[2];
         box_muller(draw(q.seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
 #pragma unroll
@@ -169,7 +170,10 @@ __global__ __launch_bounds__(256) void propose_kernel(int K, const int32_t* __re
 hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
                           const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    propose_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
+    if (K <= 128)   // one wave per particle when the draw is short (the log ratio needs one wave)
+        propose_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
+    else
+        propose_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
     return hipGetLastError();
 }
 
@@ -177,7 +181,8 @@ hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t
 // beta = 1 (Sec. 2.4, eq. (GMM beta=1)), where gamma = 0 drops the current state, so
 // v = m_j + sqrt(s_j) z on the active modes and v = z elsewhere; the component and the normals are
 // the ones a pCN-GM move of the same particle would draw at this counter.
-__global__ __launch_bounds__(256) void gm_draw_kernel(int K, const int32_t* __restrict__ slot, uint64_t seed,
+template <int NT>
+__global__ __launch_bounds__(NT) void gm_draw_kernel(int K, const int32_t* __restrict__ slot, uint64_t seed,
                                                       uint64_t ctr, int M, int kr, const double* __restrict__ logw,
                                                       const double* __restrict__ mean,
                                                       const double* __restrict__ scale, double* __restrict__ v) {
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(256) void gm_draw_kernel(int K, const int32_t* __re
     const int j = comp;
     double* vp = v + n * K;
     const int nb = (K + 1) / 2;
-    for (int blk = threadIdx.x; blk < nb; blk += 256) {
+    for (int blk = threadIdx.x; blk < nb; blk += NT) {
         double z[2];
         box_muller(draw(seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
 #pragma unroll
@@ -204,13 +209,17 @@ __global__ __launch_bounds__(256) void gm_draw_kernel(int K, const int32_t* __re
 hipError_t launch_gm_draw(int64_t N, int K, const int32_t* slot, uint64_t seed, uint64_t ctr, int M, int kr,
                           const double* logw, const double* mean, const double* scale, double* v, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    gm_draw_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, slot, seed, ctr, M, kr, logw, mean, scale, v);
+    if (K <= 128)
+        gm_draw_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, slot, seed, ctr, M, kr, logw, mean, scale, v);
+    else
+        gm_draw_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, slot, seed, ctr, M, kr, logw, mean, scale, v);
     return hipGetLastError();
 }
 
 // Metropolis-Hastings decision (Alg. 2): log a = min(0, tau (Phi(xi) - Phi(v)) + log R);
 // accept iff log U_acc < log a; a proposal without a finite potential or log R is rejected.
-__global__ __launch_bounds__(256) void accept_kernel(int K, MoveParams q, const double* __restrict__ v,
+template <int NT>
+__global__ __launch_bounds__(NT) void accept_kernel(int K, MoveParams q, const double* __restrict__ v,
                                                      const double* __restrict__ logr,
                                                      const double* __restrict__ phinew, double* __restrict__ xi,
                                                      double* __restrict__ phi, int32_t* __restrict__ n_acc) {
@@ -234,14 +243,17 @@ __global__ __launch_bounds__(256) void accept_kernel(int K, MoveParams q, const 
     }
     __syncthreads();
     if (acc) {
-        for (int k = threadIdx.x; k < K; k += 256) xi[n * K + k] = v[n * K + k];
+        for (int k = threadIdx.x; k < K; k += NT) xi[n * K + k] = v[n * K + k];
     }
 }
 
 hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
                          const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    accept_kernel<<<dim3((unsigned)N), dim3(256), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
+    if (K <= 128)
+        accept_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
+    else
+        accept_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
     return hipGetLastError();
 }
 
