@@ -17,8 +17,9 @@
 // not grow with the grid).  L^{-1} = S diag(1 / (lam_k + lam_l)) S with the orthonormal
 // symmetric sine transform S[a][b] = sqrt(2/n) sin(pi (a+1)(b+1) / n) and
 // lam_k = sin^2(pi (k+1) / (2n)) up to a constant factor (CG is blind to it), applied as four
-// 16x16x32 bf16 MFMA products with FP32 accumulation; bf16 rounding perturbs only the
-// preconditioner, never the operator or the FP64 residual.
+// 16x16x32 MFMA products with FP32 accumulation (FP16 operands on the on-chip grids, bf16 on the
+// 256 grid); operand rounding perturbs only the preconditioner, never the operator or the FP64
+// residual.
 //
 // On-chip layout: thread t owns column c = t % n of the padded n x n block (x-node c + 1) and a
 // strip of R rows (y-nodes (t / n) R + 1 ..); nodes with index n are boundary padding with t = 0
@@ -34,6 +35,8 @@ namespace smc {
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 hf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 hf4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f32_16x16x32_bf16 lane layout, checked on the device:
 //   A[16][32]: lane supplies row lane % 16, k = 8 (lane / 16) + 0..7
@@ -41,6 +44,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 //   D[16][16]: lane holds col lane % 16, rows 4 (lane / 16) + 0..3
 __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// v_mfma_f32_16x16x32_f16: the same operand and result layout with FP16 operands.
+__device__ __forceinline__ f4 mfma_f16(hf8 a, hf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 template <int NN, int NW>
@@ -52,45 +59,57 @@ struct DstShape {
     static constexpr int SP = (NW <= NB && NB % 2 == 0) ? 2 : 1;
     static constexpr int NSG = NB / SP;       // strip groups
     static constexpr int TPW = NB * NB / (NW * SP);   // output tiles per wave and strip
-    static constexpr int LD = NN + 8;         // bf16 row stride (16-byte aligned, spreads banks)
+    static constexpr int LD = NN + 8;         // 16-bit row stride (16-byte aligned, spreads banks)
     static constexpr int LDZ = NN + 4;        // fp32 row stride of the result
     static constexpr int BYTES = 2 * NN * LD * 2 + NN * LDZ * 4;
     static_assert(NW % NSG == 0 && (NB * NB) % (NW * SP) == 0, "transform tiling");
 };
 
 template <typename T, int NN, int R, int NW>
-__device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem, const __bf16* __restrict__ Stab,
-                                          const float* __restrict__ lamtab, int c, int b, int wave, int lane) {
+__device__ __forceinline__ void dst_apply(const T (&rin)[R], double rr, unsigned char* smem,
+                                          const _Float16* __restrict__ Stab, const float* __restrict__ lamtab, int c,
+                                          int b, int wave, int lane) {
     using DS = DstShape<NN, NW>;
     constexpr int LD = DS::LD, LDZ = DS::LDZ, KS = DS::KS, TPW = DS::TPW, SP = DS::SP, NSG = DS::NSG;
-    __bf16* bufA = reinterpret_cast<__bf16*>(smem);   // R^T, later T2^T
-    __bf16* bufB = bufA + NN * LD;                    // T1, later T3
+    // FP16 operands, FP32 accumulation.  r enters scaled by 2^-e, with |r| = f 2^e and f in
+    // [0.5, 1) (rr = |r|^2, the same in every thread); S is orthonormal, so every intermediate
+    // is bounded by its Frobenius norm: below 1 before 1 / (lam_k + lam_l) and below
+    // 1 / (2 lam_0) < 3400 after it, inside FP16's range with the small high-mode values still
+    // normal.  Z is scaled back by 2^e (exact).  With bf16 operands the rounding costs CG
+    // iterations (5 instead of 3 to a 1e-3 reduction at 128^2); FP16's 3 more mantissa bits
+    // recover the exact preconditioner's count.
+    int ex = 0;
+    (void)frexp(sqrt(rr), &ex);
+    ex = ex < -120 ? -120 : (ex > 120 ? 120 : ex);   // zero, or a non-finite norm: any scale
+    const float sc = ldexpf(1.0f, -ex), unsc = ldexpf(1.0f, ex);
+    _Float16* bufA = reinterpret_cast<_Float16*>(smem);   // R^T, later T2^T
+    _Float16* bufB = bufA + NN * LD;                      // T1, later T3
     float* Z = reinterpret_cast<float*>(bufB + NN * LD);   // Z[g][c]: lanes of a row read consecutive words
     const int lr = lane & 15, lk = lane >> 4;
     const int sg = wave % NSG, wq = wave / NSG;
-    bf8 sfrag[SP][KS];   // rows (sg SP + s) 16.. of S (symmetric: also columns, as a B operand)
+    hf8 sfrag[SP][KS];   // rows (sg SP + s) 16.. of S (symmetric: also columns, as a B operand)
     float lam_col[SP];
 #pragma unroll
     for (int q = 0; q < SP; ++q) {
         const int sb = sg * SP + q;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-            sfrag[q][ks] = *reinterpret_cast<const bf8*>(Stab + (sb * 16 + lr) * NN + 32 * ks + 8 * lk);
+            sfrag[q][ks] = *reinterpret_cast<const hf8*>(Stab + (sb * 16 + lr) * NN + 32 * ks + 8 * lk);
         lam_col[q] = lamtab[sb * 16 + lr];
     }
-    {   // stage R^T[c][g] = bf16(r): the thread's strip is contiguous
-        __bf16* dst = bufA + c * LD + b * R;
+    {   // stage R^T[c][g] = fp16(r 2^-e): the thread's strip is contiguous
+        _Float16* dst = bufA + c * LD + b * R;
         if constexpr (R % 8 == 0) {
 #pragma unroll
             for (int r = 0; r < R; r += 8) {
-                bf8 v;
+                hf8 v;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = (__bf16)(float)rin[r + q];
-                *reinterpret_cast<bf8*>(dst + r) = v;
+                for (int q = 0; q < 8; ++q) v[q] = (_Float16)((float)rin[r + q] * sc);
+                *reinterpret_cast<hf8*>(dst + r) = v;
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r] = (__bf16)(float)rin[r];
+            for (int r = 0; r < R; ++r) dst[r] = (_Float16)((float)rin[r] * sc);
         }
     }
     __syncthreads();
@@ -105,16 +124,16 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
         for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const bf8 av = *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
+            const hf8 av = *reinterpret_cast<const hf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
 #pragma unroll
-            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_f16(av, sfrag[q][ks], acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < SP; ++q) {
-            bf4 o;
+            hf4 o;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = (__bf16)acc[q][v];
-            *reinterpret_cast<bf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
+            for (int v = 0; v < 4; ++v) o[v] = (_Float16)acc[q][v];
+            *reinterpret_cast<hf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
         }
     }
     __syncthreads();
@@ -126,17 +145,17 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
         for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const bf8 av = *reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
+            const hf8 av = *reinterpret_cast<const hf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
 #pragma unroll
-            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_f16(av, sfrag[q][ks], acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < SP; ++q) {
-            bf4 o;
+            hf4 o;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                o[v] = (__bf16)(acc[q][v] * __builtin_amdgcn_rcpf(lamtab[rb * 16 + 4 * lk + v] + lam_col[q]));
-            *reinterpret_cast<bf4*>(bufA + ((sg * SP + q) * 16 + lr) * LD + rb * 16 + 4 * lk) = o;
+                o[v] = (_Float16)(acc[q][v] * __builtin_amdgcn_rcpf(lamtab[rb * 16 + 4 * lk + v] + lam_col[q]));
+            *reinterpret_cast<hf4*>(bufA + ((sg * SP + q) * 16 + lr) * LD + rb * 16 + 4 * lk) = o;
         }
     }
     __syncthreads();
@@ -148,16 +167,16 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
         for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const bf8 av = *reinterpret_cast<const bf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
+            const hf8 av = *reinterpret_cast<const hf8*>(bufA + (cb * 16 + lr) * LD + 32 * ks + 8 * lk);
 #pragma unroll
-            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(av, sfrag[q][ks], acc[q]);
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_f16(av, sfrag[q][ks], acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < SP; ++q) {
-            bf4 o;
+            hf4 o;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = (__bf16)acc[q][v];
-            *reinterpret_cast<bf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
+            for (int v = 0; v < 4; ++v) o[v] = (_Float16)acc[q][v];
+            *reinterpret_cast<hf4*>(bufB + ((sg * SP + q) * 16 + lr) * LD + cb * 16 + 4 * lk) = o;
         }
     }
     __syncthreads();
@@ -169,14 +188,14 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
         for (int q = 0; q < SP; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const bf8 bv = *reinterpret_cast<const bf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
+            const hf8 bv = *reinterpret_cast<const hf8*>(bufB + (rb * 16 + lr) * LD + 32 * ks + 8 * lk);
 #pragma unroll
-            for (int q = 0; q < SP; ++q) acc[q] = mfma_bf16(sfrag[q][ks], bv, acc[q]);
+            for (int q = 0; q < SP; ++q) acc[q] = mfma_f16(sfrag[q][ks], bv, acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < SP; ++q)
             *reinterpret_cast<float4*>(Z + (rb * 16 + lr) * LDZ + (sg * SP + q) * 16 + 4 * lk) =
-                make_float4(acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
+                make_float4(acc[q][0] * unsc, acc[q][1] * unsc, acc[q][2] * unsc, acc[q][3] * unsc);
     }
     __syncthreads();
 }
@@ -185,16 +204,22 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], unsigned char* smem
 // each of N grids (row g is y-node g+1, column c is x-node c+1; padding row/column zero).
 template <int NN, int R>
 __global__ __launch_bounds__(NN * NN / R) void dst_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
-                                                               const __bf16* __restrict__ Stab,
+                                                               const _Float16* __restrict__ Stab,
                                                                const float* __restrict__ lamtab) {
     constexpr int NT = NN * NN / R, NW = NT / 64;
     __shared__ __align__(16) unsigned char smem[DstShape<NN, NW>::BYTES];
+    __shared__ double red[16];
     const int tid = threadIdx.x, c = tid % NN, b = tid / NN;
     const int64_t base = (int64_t)blockIdx.x * NN * NN;
     float r[R];
+    double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) r[k] = rin[base + (b * R + k) * NN + c];
-    dst_apply<float, NN, R, NW>(r, smem, Stab, lamtab, c, b, tid >> 6, tid & 63);
+    for (int k = 0; k < R; ++k) {
+        r[k] = rin[base + (b * R + k) * NN + c];
+        acc += (double)r[k] * (double)r[k];
+    }
+    const double rr = block_sum<NW>(acc, red);
+    dst_apply<float, NN, R, NW>(r, rr, smem, Stab, lamtab, c, b, tid >> 6, tid & 63);
     const float* Z = reinterpret_cast<const float*>(smem + 2 * NN * DstShape<NN, NW>::LD * 2);
 #pragma unroll
     for (int k = 0; k < R; ++k) zout[base + (b * R + k) * NN + c] = Z[(b * R + k) * DstShape<NN, NW>::LDZ + c];
@@ -207,12 +232,13 @@ __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restr
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
                             hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);      // the 256 grid's table (bf16)
+    const _Float16* Sh = reinterpret_cast<const _Float16*>(S);  // the on-chip grids' tables (FP16)
     switch (n) {
         case 256: dst256_apply_kernel<<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
-        case 32: dst_apply_kernel<32, 4><<<dim3((unsigned)N), dim3(256), 0, s>>>(r, z, Sb, lam); break;
-        case 64: dst_apply_kernel<64, 8><<<dim3((unsigned)N), dim3(512), 0, s>>>(r, z, Sb, lam); break;
-        case 128: dst_apply_kernel<128, 16><<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
+        case 32: dst_apply_kernel<32, 4><<<dim3((unsigned)N), dim3(256), 0, s>>>(r, z, Sh, lam); break;
+        case 64: dst_apply_kernel<64, 8><<<dim3((unsigned)N), dim3(512), 0, s>>>(r, z, Sh, lam); break;
+        case 128: dst_apply_kernel<128, 16><<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sh, lam); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -435,7 +461,7 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, double* 
 template <typename T, int NN, int R, bool DST, bool ADJ>
 __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t row, const int32_t* __restrict__ obs,
                                                unsigned char* smem, SolveShared& sh,
-                                               const __bf16* __restrict__ Stab, const float* __restrict__ lamtab) {
+                                               const _Float16* __restrict__ Stab, const float* __restrict__ lamtab) {
     constexpr int NT = NN * NN / R;
     constexpr int NW = NT / 64;
     constexpr int NP1 = NN + 1;
@@ -494,9 +520,9 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
 
     // z = L^{-1} r into Z[g][c] (LDS), with the barriers of the four products
     int napp = 0;   // preconditioner applications (same in every thread)
-    auto precondition = [&](const T (&rin)[R]) __attribute__((always_inline)) {
+    auto precondition = [&](const T (&rin)[R], double rrin) __attribute__((always_inline)) {
         if constexpr (DST) {
-            dst_apply<T, NN, R, NW>(rin, smem, Stab, lamtab, c, b, wave, lane);
+            dst_apply<T, NN, R, NW>(rin, rrin, smem, Stab, lamtab, c, b, wave, lane);
             ++napp;
         }
     };
@@ -621,15 +647,15 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
             }
             double rr, rz;
             if constexpr (DST) {
+                rr = block_sum<NW>(tacc, red1);   // also the transform's input scale
                 __syncthreads();                  // the transform buffers alias the staging slots
-                precondition(rv);
+                precondition(rv, rr);
                 double zacc = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     p[r] = zval(r);
                     zacc += (double)rv[r] * (double)p[r];
                 }
-                rr = block_sum<NW>(tacc, red1);
                 rz = block_sum<NW>(zacc, red2);
             } else {
 #pragma unroll
@@ -677,7 +703,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
                 ++total;
                 if (!(rr > target)) break;
                 if constexpr (DST) {
-                    precondition(rv);
+                    precondition(rv, rr);
                     T z[R];
                     T rz_acc = T(0);
 #pragma unroll
@@ -733,7 +759,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
 }
 
 template <typename T, int NN, int R, bool DST, bool ADJ>
-__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const __bf16* __restrict__ Stab,
+__global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const _Float16* __restrict__ Stab,
                                                          const float* __restrict__ lamtab) {
     __shared__ __align__(16) unsigned char smem[onchip_smem<T, NN, R, DST>()];
     __shared__ SolveShared sh;
@@ -1234,10 +1260,11 @@ bool mixed_supported(int n) { return n == 64 || n == 128 || n == 256; }
 __shared__ SolveShared g_mixed_sh;
 
 template <typename T, int NN, int R, bool DST>
-__device__ __noinline__ void mixed_onchip(const SolveArgs& a, int64_t p, const int32_t* obs, const __bf16* S,
+__device__ __noinline__ void mixed_onchip(const SolveArgs& a, int64_t p, const int32_t* obs, const void* S,
                                           const float* lam) {
     static_assert(onchip_smem<T, NN, R, DST>() <= MIXED_SMEM, "mixed-grid LDS");
-    cg_onchip_body<T, NN, R, DST, false>(a, p, obs, g_mixed_smem, g_mixed_sh, S, lam);
+    cg_onchip_body<T, NN, R, DST, false>(a, p, obs, g_mixed_smem, g_mixed_sh, reinterpret_cast<const _Float16*>(S),
+                                         lam);
 }
 
 template <typename T>
@@ -1245,9 +1272,10 @@ __device__ __noinline__ void mixed_global(const SolveArgs& a, int64_t p, int n, 
     cg_global_body<T, false>(a, p, n, obs, g_mixed_sh);
 }
 
-__device__ __noinline__ void mixed_global_dst256(const SolveArgs& a, int64_t p, const int32_t* obs, const __bf16* S,
+__device__ __noinline__ void mixed_global_dst256(const SolveArgs& a, int64_t p, const int32_t* obs, const void* S,
                                                  const float* lam) {
-    cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<__bf16*>(g_mixed_smem), S, lam);
+    cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<__bf16*>(g_mixed_smem),
+                                       reinterpret_cast<const __bf16*>(S), lam);
 }
 
 template <int PREC, bool DST>
@@ -1267,7 +1295,7 @@ __global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTab
         const int64_t p = __builtin_amdgcn_readfirstlane(list[item]);
         const int l = __builtin_amdgcn_readfirstlane(level[p]);
         const int n = (l >= 0 && l < lt.n_levels) ? lt.n[l] : 0;
-        const __bf16* S = n ? reinterpret_cast<const __bf16*>(lt.S[l]) : nullptr;
+        const void* S = n ? lt.S[l] : nullptr;   // FP16 table up to 128, bf16 at 256
         if constexpr (PREC == SMC_FP32_REFINE) {
             if (n == 64)
                 mixed_onchip<float, 64, 4, DST>(a, p, lt.obs[l], S, lt.lam[l]);
@@ -1323,7 +1351,7 @@ hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a,
 
 template <typename T, int NN, int R, bool DST>
 static hipError_t run_onchip(int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
-    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+    const _Float16* Sb = reinterpret_cast<const _Float16*>(S);
     if (a.lam)
         cg_onchip<T, NN, R, DST, true><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, Sb, lam);
     else
