@@ -326,9 +326,8 @@ int smc_gather(int64_t N, int32_t K, const int32_t* idx, const double* xi_in,
 
 /* The fast-Poisson preconditioner of the forward solves by itself (for tests): for each of N
  * grids, z = L^{-1} r with L the constant-coefficient Dirichlet Laplacian of grid `level`, up
- * to a positive constant factor, computed with sine transforms on the matrix cores: FP16
- * operands (the input scaled by a power of two from its norm, the result scaled back) on grids
- * up to 128, bf16 at 256.
+ * to a positive constant factor, computed with sine transforms on the matrix cores in FP16 (the
+ * input scaled by a power of two from its norm, the result scaled back).
  * r, z: [N][n][n] FP32, element [g][c] for the node ((c+1)/n, (g+1)/n); index n-1 is boundary
  * padding and must hold 0 in r.  Grids of 32, 64, 128 and 256 intervals. */
 int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, float* z, smc_stream stream);

@@ -202,8 +202,8 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
         ck(upload(&P.lv[l].obs_node, nodes.data(), nodes.size()));
         if (P.dim == 2 && dst_supported(n)) {
             // S[a][b] = sqrt(2/n) sin(pi (a+1)(b+1) / n) for nodes a+1, b+1 = 1..n; the last row and
-            // column (the boundary padding node n) are exactly zero.  FP16 for the on-chip solvers
-            // (grids up to 128, which scale their operands into FP16's range), bf16 for the 256 grid
+            // column (the boundary padding node n) are exactly zero.  FP16: the solvers scale their
+            // transform operands into FP16's range
             std::vector<double> S((size_t)n * n);
             std::vector<float> lam(n);
             for (int r = 0; r < n; ++r) {
@@ -213,15 +213,9 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
                                                ? 0.0
                                                : std::sqrt(2.0 / n) * std::sin(M_PI * (double)((r + 1) * (q + 1)) / n);
             }
-            if (n <= 128) {
-                std::vector<_Float16> Sh(S.size());
-                for (size_t k = 0; k < S.size(); ++k) Sh[k] = (_Float16)(float)S[k];
-                ck(upload((_Float16**)&P.lv[l].dst_S, Sh.data(), Sh.size()));
-            } else {
-                std::vector<__bf16> Sb(S.size());
-                for (size_t k = 0; k < S.size(); ++k) Sb[k] = (__bf16)(float)S[k];
-                ck(upload((__bf16**)&P.lv[l].dst_S, Sb.data(), Sb.size()));
-            }
+            std::vector<_Float16> Sh(S.size());
+            for (size_t k = 0; k < S.size(); ++k) Sh[k] = (_Float16)(float)S[k];
+            ck(upload((_Float16**)&P.lv[l].dst_S, Sh.data(), Sh.size()));
             ck(upload(&P.lv[l].dst_lam, lam.data(), lam.size()));
         }
     }

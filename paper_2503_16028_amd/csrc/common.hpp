@@ -22,7 +22,7 @@ struct Level {
     int n = 0;                   // intervals per axis
     double* basis = nullptr;     // 2D: [(n+1)][KLP] c_k cos(k pi i / n); 1D: [(n+1)][kl] sqrt2 sin(k pi i / n)
     int32_t* obs_node = nullptr; // [n_obs] flat nodal index (2D j*(n+1)+i, 1D i)
-    void* dst_S = nullptr;       // [n][n] sine transform (fast-Poisson preconditioner): FP16 up to 128, bf16 at 256
+    void* dst_S = nullptr;       // [n][n] FP16 sine transform (fast-Poisson preconditioner)
     float* dst_lam = nullptr;    // [n] its 1D eigenvalues sin^2(pi (k+1) / 2n)
     int rows = 0;                // tile of the fast-Poisson solver: grid rows per thread (0 = default)
 };
@@ -202,7 +202,7 @@ struct LevelTable {
     int n[MAX_LEVELS];
     const double* basis[MAX_LEVELS];
     const int32_t* obs[MAX_LEVELS];
-    const void* S[MAX_LEVELS];       // sine transform (FP16 up to 128, bf16 at 256), or null
+    const void* S[MAX_LEVELS];       // FP16 sine transform, or null
     const float* lam[MAX_LEVELS];
 };
 

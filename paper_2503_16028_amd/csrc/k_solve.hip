@@ -17,8 +17,8 @@
 // not grow with the grid).  L^{-1} = S diag(1 / (lam_k + lam_l)) S with the orthonormal
 // symmetric sine transform S[a][b] = sqrt(2/n) sin(pi (a+1)(b+1) / n) and
 // lam_k = sin^2(pi (k+1) / (2n)) up to a constant factor (CG is blind to it), applied as four
-// 16x16x32 MFMA products with FP32 accumulation (FP16 operands on the on-chip grids, bf16 on the
-// 256 grid); operand rounding perturbs only the preconditioner, never the operator or the FP64
+// 16x16x32 FP16 MFMA products with FP32 accumulation, the input scaled by a power of two from
+// its norm; operand rounding perturbs only the preconditioner, never the operator or the FP64
 // residual.
 //
 // On-chip layout: thread t owns column c = t % n of the padded n x n block (x-node c + 1) and a
@@ -32,22 +32,24 @@
 
 namespace smc {
 
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 hf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 hf4 __attribute__((ext_vector_type(4)));
 
-// v_mfma_f32_16x16x32_bf16 lane layout, checked on the device:
+// v_mfma_f32_16x16x32_f16 lane layout (the bf16 instruction's too), checked on the device:
 //   A[16][32]: lane supplies row lane % 16, k = 8 (lane / 16) + 0..7
 //   B[32][16]: lane supplies col lane % 16, k = 8 (lane / 16) + 0..7
 //   D[16][16]: lane holds col lane % 16, rows 4 (lane / 16) + 0..3
-__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-// v_mfma_f32_16x16x32_f16: the same operand and result layout with FP16 operands.
 __device__ __forceinline__ f4 mfma_f16(hf8 a, hf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// The exponent e of |r| = f 2^e, f in [0.5, 1), from rr = |r|^2; clamped, so that a zero or
+// non-finite norm still gives a usable scale.  The transforms take their FP16 input as r 2^-e.
+__device__ __forceinline__ int norm_exponent(double rr) {
+    int ex = 0;
+    (void)frexp(sqrt(rr), &ex);
+    return ex < -120 ? -120 : (ex > 120 ? 120 : ex);
 }
 
 template <int NN, int NW>
@@ -76,11 +78,9 @@ __device__ __forceinline__ void dst_apply(const T (&rin)[R], double rr, unsigned
     // is bounded by its Frobenius norm: below 1 before 1 / (lam_k + lam_l) and below
     // 1 / (2 lam_0) < 3400 after it, inside FP16's range with the small high-mode values still
     // normal.  Z is scaled back by 2^e (exact).  With bf16 operands the rounding costs CG
-    // iterations (5 instead of 3 to a 1e-3 reduction at 128^2); FP16's 3 more mantissa bits
+    // iterations (5 instead of 3 to a 1e-3 reduction at 128^2); FP16's 3 more significand bits
     // recover the exact preconditioner's count.
-    int ex = 0;
-    (void)frexp(sqrt(rr), &ex);
-    ex = ex < -120 ? -120 : (ex > 120 ? 120 : ex);   // zero, or a non-finite norm: any scale
+    const int ex = norm_exponent(rr);
     const float sc = ldexpf(1.0f, -ex), unsc = ldexpf(1.0f, ex);
     _Float16* bufA = reinterpret_cast<_Float16*>(smem);   // R^T, later T2^T
     _Float16* bufB = bufA + NN * LD;                      // T1, later T3
@@ -226,16 +226,15 @@ __global__ __launch_bounds__(NN * NN / R) void dst_apply_kernel(const float* __r
 }
 
 __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
-                                                            const __bf16* __restrict__ Stab,
+                                                            const _Float16* __restrict__ Stab,
                                                             const float* __restrict__ lamtab);
 
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
                             hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const __bf16* Sb = reinterpret_cast<const __bf16*>(S);      // the 256 grid's table (bf16)
-    const _Float16* Sh = reinterpret_cast<const _Float16*>(S);  // the on-chip grids' tables (FP16)
+    const _Float16* Sh = reinterpret_cast<const _Float16*>(S);
     switch (n) {
-        case 256: dst256_apply_kernel<<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sb, lam); break;
+        case 256: dst256_apply_kernel<<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sh, lam); break;
         case 32: dst_apply_kernel<32, 4><<<dim3((unsigned)N), dim3(256), 0, s>>>(r, z, Sh, lam); break;
         case 64: dst_apply_kernel<64, 8><<<dim3((unsigned)N), dim3(512), 0, s>>>(r, z, Sh, lam); break;
         case 128: dst_apply_kernel<128, 16><<<dim3((unsigned)N), dim3(1024), 0, s>>>(r, z, Sh, lam); break;
@@ -771,7 +770,7 @@ __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const _Flo
 // the nodes of one particle.
 // The fast-Poisson preconditioner z = L^{-1} r of a 256 x 256 grid whose vectors live in global
 // memory (one workgroup of 16 waves).  L^{-1} = S diag(1 / (lam_i + lam_j)) S is applied as four
-// passes X <- (X S)^T over a single bf16 copy of the grid in LDS: each pass is a batch of
+// passes X <- (X S)^T over a single FP16 copy of the grid in LDS: each pass is a batch of
 // independent 1D sine transforms along the rows, and the transposed write-back turns the next pass
 // into the transform along the other axis.  Wave w owns output columns 16w..16w+15, keeps its
 // 16-column slice of S in registers, holds its 16 result tiles until every wave has read X, then
@@ -786,43 +785,48 @@ constexpr int MIXED_SMEM = cmax(onchip_smem<float, 128, 16, true>(),
                                 cmax(onchip_smem<float, 64, 4, true>(), onchip_smem<double, 64, 4, false>()));
 __shared__ __align__(16) unsigned char g_mixed_smem[MIXED_SMEM];
 
-// With `staged`, X already holds bf16(r) (written by the caller's residual update); with `rz`,
-// the thread's share of sum r z is accumulated while z is stored.
-__device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, __bf16* X,
-                                             const __bf16* __restrict__ S, const float* __restrict__ lam,
+// FP16 operands as in dst_apply: X holds fp16(r 2^-ex) and z is scaled back by 2^ex.  With
+// `staged`, X already holds it (written by the caller's residual update with the same ex); with
+// `rz`, the thread's share of sum r z is accumulated while z is stored.
+__device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float* __restrict__ z, _Float16* X,
+                                             const _Float16* __restrict__ S, const float* __restrict__ lam, int ex,
                                              bool staged = false, double* rz = nullptr) {
     constexpr int NN = 256, LD = D256_LD, KS = 8, NB = 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4, cb = wave;
-    bf8 sB[KS];   // B operand: S[k][16 cb + lr] = S[16 cb + lr][k] (S is symmetric)
+    const float sc = ldexpf(1.0f, -ex), unsc = ldexpf(1.0f, ex);
+    hf8 sB[KS];   // B operand: S[k][16 cb + lr] = S[16 cb + lr][k] (S is symmetric)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) sB[ks] = *reinterpret_cast<const bf8*>(S + (16 * cb + lr) * NN + 32 * ks + 8 * lk);
-    for (int e = staged ? NN * NN : tid; e < NN * NN / 8; e += 1024) {   // X = bf16(r), row-major
+    for (int ks = 0; ks < KS; ++ks) sB[ks] = *reinterpret_cast<const hf8*>(S + (16 * cb + lr) * NN + 32 * ks + 8 * lk);
+    for (int e = staged ? NN * NN : tid; e < NN * NN / 8; e += 1024) {   // X = fp16(r 2^-ex), row-major
         const int g = e >> 5, c0 = (e & 31) * 8;
         const float4 u0 = *reinterpret_cast<const float4*>(r + g * NN + c0);
         const float4 u1 = *reinterpret_cast<const float4*>(r + g * NN + c0 + 4);
-        bf8 v;
-        v[0] = (__bf16)u0.x; v[1] = (__bf16)u0.y; v[2] = (__bf16)u0.z; v[3] = (__bf16)u0.w;
-        v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
-        *reinterpret_cast<bf8*>(X + g * LD + c0) = v;
+        hf8 v;
+        v[0] = (_Float16)(u0.x * sc); v[1] = (_Float16)(u0.y * sc); v[2] = (_Float16)(u0.z * sc);
+        v[3] = (_Float16)(u0.w * sc); v[4] = (_Float16)(u1.x * sc); v[5] = (_Float16)(u1.y * sc);
+        v[6] = (_Float16)(u1.z * sc); v[7] = (_Float16)(u1.w * sc);
+        *reinterpret_cast<hf8*>(X + g * LD + c0) = v;
     }
     __syncthreads();
     const float lam_c = lam[16 * cb + lr];
 #pragma unroll 1
     for (int step = 0; step < 4; ++step) {
-        bf4 out[NB];
+        hf4 out[NB];
 #pragma unroll
         for (int ra = 0; ra < NB; ++ra) {   // P[i][j] = sum_k X[i][k] S[k][j], i in row tile ra, j in cb
             f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
-                acc = mfma_bf16(*reinterpret_cast<const bf8*>(X + (16 * ra + lr) * LD + 32 * ks + 8 * lk), sB[ks], acc);
+                acc = mfma_f16(*reinterpret_cast<const hf8*>(X + (16 * ra + lr) * LD + 32 * ks + 8 * lk), sB[ks], acc);
             if (step == 1) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[v] *= __builtin_amdgcn_rcpf(lam[16 * ra + 4 * lk + v] + lam_c);
             }
             if (step == 3) {   // z[j][i] = P[i][j]
                 const int at = (16 * cb + lr) * NN + 16 * ra + 4 * lk;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] *= unsc;
                 *reinterpret_cast<float4*>(z + at) = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 if (rz) {
                     const float4 rv4 = *reinterpret_cast<const float4*>(r + at);
@@ -831,13 +835,13 @@ __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float*
                 }
             } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) out[ra][v] = (__bf16)acc[v];
+                for (int v = 0; v < 4; ++v) out[ra][v] = (_Float16)acc[v];
             }
         }
         if (step < 3) {
             __syncthreads();   // every wave has finished reading X
 #pragma unroll
-            for (int ra = 0; ra < NB; ++ra) *reinterpret_cast<bf4*>(X + (16 * cb + lr) * LD + 16 * ra + 4 * lk) = out[ra];
+            for (int ra = 0; ra < NB; ++ra) *reinterpret_cast<hf4*>(X + (16 * cb + lr) * LD + 16 * ra + 4 * lk) = out[ra];
             __syncthreads();
         }
     }
@@ -846,21 +850,25 @@ __device__ __forceinline__ void dst256_apply(const float* __restrict__ r, float*
 
 // The 256^2 transform as a function of its own, on the module-level buffer both 256^2 solvers
 // stage X in: inlined into the CG loop it competes for that loop's registers and both spill.
-// Returns this thread's share of r.z when `staged` (r already in X as bf16), else 0.
+// Returns this thread's share of r.z when `staged` (r already in X as fp16(r 2^-ex)), else 0.
 static_assert(D256_BYTES <= MIXED_SMEM, "256^2 transform LDS");
-__device__ __noinline__ double dst256_precondition(const float* r, float* z, const __bf16* S, const float* lam,
-                                                   int staged) {
+__device__ __noinline__ double dst256_precondition(const float* r, float* z, const _Float16* S, const float* lam,
+                                                   int staged, int ex) {
     double rz = 0.0;
-    dst256_apply(r, z, reinterpret_cast<__bf16*>(g_mixed_smem), S, lam, staged != 0, staged ? &rz : nullptr);
+    dst256_apply(r, z, reinterpret_cast<_Float16*>(g_mixed_smem), S, lam, ex, staged != 0, staged ? &rz : nullptr);
     return rz;
 }
 
 __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
-                                                            const __bf16* __restrict__ Stab,
+                                                            const _Float16* __restrict__ Stab,
                                                             const float* __restrict__ lamtab) {
-    __shared__ __align__(16) __bf16 X[256 * D256_LD];
+    __shared__ __align__(16) _Float16 X[256 * D256_LD];
+    __shared__ double red[16];
     const int64_t base = (int64_t)blockIdx.x * 256 * 256;
-    dst256_apply(rin + base, zout + base, X, Stab, lamtab);
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < 256 * 256; k += 1024) acc += (double)rin[base + k] * (double)rin[base + k];
+    const double rr = block_sum<16>(acc, red);
+    dst256_apply(rin + base, zout + base, X, Stab, lamtab, norm_exponent(rr) + 3);
 }
 
 // DST: fast-Poisson-preconditioned CG (grid 256 only, T = float, X = D256_BYTES of LDS);
@@ -868,7 +876,7 @@ __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restr
 template <typename T, bool ADJ, bool DST = false>
 __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t row, const int NN,
                                                const int32_t* __restrict__ obs, SolveShared& sh,
-                                               __bf16* X = nullptr, const __bf16* __restrict__ Stab = nullptr,
+                                               _Float16* X = nullptr, const _Float16* __restrict__ Stab = nullptr,
                                                const float* __restrict__ lamtab = nullptr) {
     constexpr int NW = 16;
     static_assert(!DST || sizeof(T) == 4, "the preconditioned global solver runs in FP32");
@@ -893,10 +901,11 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     auto interior = [&](int g, int c) { return c < NN - 1 && g < NN - 1; };
     int napp = 0;
-    auto precondition = [&]() {   // zv = L^{-1} rv
+    auto precondition = [&](double rrin) {   // zv = L^{-1} rv, rrin = |rv|^2
         if constexpr (DST) {
+            // the input at a 2^-3 margin below unit norm, as for the staged applications below
             (void)dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), Stab, lamtab,
-                                      0);
+                                      0, norm_exponent(rrin) + 3);
             ++napp;
         }
     };
@@ -993,7 +1002,7 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             double rr = block_sum<NW>(tacc, red1);
             double rz = rr;
             if constexpr (DST) {   // p = z = L^{-1} r
-                precondition();
+                precondition(rr);
                 double zacc = 0.0;
                 for (int k = tid; k < nodes; k += 1024) {
                     zacc += (double)rv[k] * (double)zv[k];
@@ -1008,10 +1017,16 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             bool broke = false;
             if constexpr (DST) {
                 // Per iteration four passes over the global vectors: the stencil (t p of the
-                // neighbours formed on the fly), the x/r update (which also stages bf16(r) for the
-                // transform in LDS), the transform (z stored, r.z accumulated), the p update.
+                // neighbours formed on the fly), the x/r update (which also stages fp16(r 2^-ex) for
+                // the transform in LDS), the transform (z stored, r.z accumulated), the p update.
+                // The staged scale comes from the norm before the update (the new one is summed
+                // in the same pass), 2^-3 below unit norm: the residual would have to grow 39-fold
+                // in one iteration to overflow FP16 (the largest intermediate is then below
+                // 1 / (2 lam_0) / 8 < 1700 times the growth).
                 while (rr > target) {
                     if (total >= a.max_iter) break;
+                    const int ex = norm_exponent(rr) + 3;
+                    const float sc = ldexpf(1.0f, -ex);
                     T pq_acc = T(0);
                     for (int k = 4 * tid; k < nodes; k += 4096) {   // four consecutive nodes of a row
                         const int g = k / NN, c = k % NN;
@@ -1055,16 +1070,17 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                         r_acc += ((r4.x * r4.x + r4.y * r4.y) + (r4.z * r4.z + r4.w * r4.w));
                         *reinterpret_cast<float4*>(xv + k) = x4;
                         *reinterpret_cast<float4*>(rv + k) = r4;
-                        bf4 b;
-                        b[0] = (__bf16)r4.x; b[1] = (__bf16)r4.y; b[2] = (__bf16)r4.z; b[3] = (__bf16)r4.w;
-                        *reinterpret_cast<bf4*>(X + (k / NN) * D256_LD + (k % NN)) = b;
+                        hf4 b;
+                        b[0] = (_Float16)(r4.x * sc); b[1] = (_Float16)(r4.y * sc);
+                        b[2] = (_Float16)(r4.z * sc); b[3] = (_Float16)(r4.w * sc);
+                        *reinterpret_cast<hf4*>(X + (k / NN) * D256_LD + (k % NN)) = b;
                     }
                     rr = block_sum<NW>((double)r_acc, red2);   // its barrier also publishes X
                     ++total;
                     if (!(rr > target)) break;
                     double zacc = 0.0;
                     zacc = dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), Stab,
-                                               lamtab, 1);
+                                               lamtab, 1, ex);
                     ++napp;
                     const double rzn = block_sum<NW>(zacc, red1);
                     const T beta = (T)(rzn / rz);
@@ -1147,10 +1163,10 @@ __global__ __launch_bounds__(1024) void cg_global(SolveArgs a, int NN) {
 }
 
 template <bool ADJ>
-__global__ __launch_bounds__(1024) void cg_global_dst256(SolveArgs a, const __bf16* __restrict__ Stab,
+__global__ __launch_bounds__(1024) void cg_global_dst256(SolveArgs a, const _Float16* __restrict__ Stab,
                                                          const float* __restrict__ lamtab) {
     __shared__ SolveShared sh;
-    cg_global_body<float, ADJ, true>(a, blockIdx.x, 256, a.obs, sh, reinterpret_cast<__bf16*>(g_mixed_smem), Stab,
+    cg_global_body<float, ADJ, true>(a, blockIdx.x, 256, a.obs, sh, reinterpret_cast<_Float16*>(g_mixed_smem), Stab,
                                      lamtab);
 }
 
@@ -1274,8 +1290,8 @@ __device__ __noinline__ void mixed_global(const SolveArgs& a, int64_t p, int n, 
 
 __device__ __noinline__ void mixed_global_dst256(const SolveArgs& a, int64_t p, const int32_t* obs, const void* S,
                                                  const float* lam) {
-    cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<__bf16*>(g_mixed_smem),
-                                       reinterpret_cast<const __bf16*>(S), lam);
+    cg_global_body<float, false, true>(a, p, 256, obs, g_mixed_sh, reinterpret_cast<_Float16*>(g_mixed_smem),
+                                       reinterpret_cast<const _Float16*>(S), lam);
 }
 
 template <int PREC, bool DST>
@@ -1295,7 +1311,7 @@ __global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTab
         const int64_t p = __builtin_amdgcn_readfirstlane(list[item]);
         const int l = __builtin_amdgcn_readfirstlane(level[p]);
         const int n = (l >= 0 && l < lt.n_levels) ? lt.n[l] : 0;
-        const void* S = n ? lt.S[l] : nullptr;   // FP16 table up to 128, bf16 at 256
+        const void* S = n ? lt.S[l] : nullptr;   // FP16 sine table
         if constexpr (PREC == SMC_FP32_REFINE) {
             if (n == 64)
                 mixed_onchip<float, 64, 4, DST>(a, p, lt.obs[l], S, lt.lam[l]);
@@ -1401,7 +1417,7 @@ hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, co
         case 128 * 64 + 0:
         case 128 * 64 + 32: return run_onchip<float, 128, 32, true>(N, a, S, lam, s);
         case 256 * 64 + 0: {
-            const __bf16* Sb = reinterpret_cast<const __bf16*>(S);
+            const _Float16* Sb = reinterpret_cast<const _Float16*>(S);
             if (a.lam)
                 cg_global_dst256<true><<<dim3((unsigned)N), dim3(1024), 0, s>>>(a, Sb, lam);
             else
