@@ -1082,7 +1082,16 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                     zacc = dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv), Stab,
                                                lamtab, 1, ex);
                     ++napp;
-                    const double rzn = block_sum<NW>(zacc, red1);
+                    double rzn = block_sum<NW>(zacc, red1);
+                    if (!(fabs(rzn) < INFINITY)) {   // the residual outgrew the staged scale: redo from r
+                        __syncthreads();
+                        zacc = dst256_precondition(reinterpret_cast<const float*>(rv), reinterpret_cast<float*>(zv),
+                                                   Stab, lamtab, 0, norm_exponent(rr) + 3);
+                        double zacc2 = 0.0;
+                        for (int k = tid; k < nodes; k += 1024) zacc2 += (double)rv[k] * (double)zv[k];
+                        rzn = block_sum<NW>(zacc2, red2);
+                        ++napp;
+                    }
                     const T beta = (T)(rzn / rz);
                     rz = rzn;
                     for (int k = 4 * tid; k < nodes; k += 4096) {
