@@ -510,7 +510,7 @@ static hipError_t forward_levels(smc_problem_s* ps, int prec, int64_t N, const d
     a.stats = P.profiling ? P.stats : nullptr;
     const bool rec = P.profiling && !ps->capturing;
     if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
-    const bool dst = prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO;
+    const bool dst = P.precond == SMC_PRECOND_AUTO;
     e = launch_solve_mixed(prec, dst, N, a, lt, o.level, P.ws_list, P.ws_counters, P.n_cu, s);
     if (e != hipSuccess) return e;
     if (rec) e = record(ps->pool, s);
@@ -544,6 +544,8 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
         e = launch_solve1d(L.n, N, a, s);
     else if (prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S)
         e = launch_solve2d_dst(L.n, L.rows, N, a, L.dst_S, L.dst_lam, s);
+    else if (prec == SMC_FP64 && P.precond == SMC_PRECOND_AUTO && L.dst_S && (L.n == 128 || L.n == 256))
+        e = launch_solve2d_dst64(L.n, N, a, L.dst_S, L.dst_lam, s);
     else
         e = launch_solve2d(L.n, prec, N, a, s);
     if (e != hipSuccess) return e;
