@@ -183,6 +183,25 @@ def test_forward_fp32_jacobi_only(name, grid, N):
     assert (it.cpu().numpy() > 3 * grid).all()          # Jacobi needs O(n) iterations per decade
 
 
+@pytest.mark.parametrize("name,grid,N", [("c3", 128, 2), ("c5", 256, 1)])
+def test_forward_fp64_jacobi_only(name, grid, N):
+    """The Jacobi-scaled FP64 global-memory path (the fast-Poisson one is the default)."""
+    from paper_2503_16028_amd import smc
+    banner("forward fp64 jacobi", name, grid, N)
+    d, op = load(name)
+    p = gpu_problem(d, N, grids=[grid], tol64=TOL64[grid], max_iter=60 * grid, max_sweeps=6,
+                    precond=smc.PRECOND_JACOBI)
+    xi = inputs.particles(N, op.K, 8)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP64, G, it)
+    torch.cuda.synchronize()
+    ref = oracle_G(op, xi, grid)
+    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert (it.cpu().numpy() > 3 * grid).all()          # Jacobi needs O(n) iterations per decade
+    assert smc.smc_status_flags(p) == 0
+
+
 @pytest.mark.parametrize("name,grid", [("t1", 16), ("t1", 64), ("c1", 64)])
 def test_forward_1d(name, grid):
     from paper_2503_16028_amd import smc
