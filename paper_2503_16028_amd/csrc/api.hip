@@ -63,7 +63,7 @@ static void free_problem(Problem& P) {
     f(P.ws_v); f(P.ws_logr); f(P.ws_phinew); f(P.ws_e); f(P.ws_x64); f(P.ws_lam); f(P.ws_gnew); f(P.ws_sd);
     f(P.ws_vec);
     f(P.ws_G); f(P.ws_iters); f(P.ws_list); f(P.ws_counters); f(P.flags); f(P.stats);
-    f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers);
+    f(P.ws_fit_d2); f(P.ws_fit_par); f(P.ws_fit_part); f(P.ws_fit_centers); f(P.ws_mixtab);
     f(P.mix_c);
 }
 
@@ -246,6 +246,7 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
         ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * GM_PAR));
         ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * pe));
         ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
+        ck(hipMalloc((void**)&P.ws_mixtab, sizeof(double) * MAX_LEVELS * MIXTAB));
     }
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
@@ -312,6 +313,7 @@ extern "C" int smc_problem_create_l2mix(const smc_l2mix_desc* d, smc_problem* ou
     ck(hipMalloc((void**)&P.ws_fit_par, sizeof(double) * 2 * GM_PAR));
     ck(hipMalloc((void**)&P.ws_fit_part, sizeof(double) * em_blocks(Nm) * MAX_M * (1 + 2 * MAX_KR)));
     ck(hipMalloc((void**)&P.ws_fit_centers, sizeof(int32_t) * MAX_M));
+    ck(hipMalloc((void**)&P.ws_mixtab, sizeof(double) * MAX_LEVELS * MIXTAB));
     ck(hipMalloc((void**)&P.flags, sizeof(int32_t)));
     ck(hipMalloc((void**)&P.stats, 4 * sizeof(unsigned long long)));
     ck(hipMemset(P.stats, 0, 4 * sizeof(unsigned long long)));
@@ -655,9 +657,10 @@ static int move_loop(smc_problem_s* p, int64_t N, MoveParams q, int32_t n_moves,
     if (N <= 0) return SMC_OK;
     HIPCHK(launch_fill_i32(n_acc, N, 0, s));
     if (level) HIPCHK(launch_plan(N, level, level_table(P), P.ws_list, P.ws_counters, P.flags, s));
+    if (n_moves > 0) HIPCHK(launch_mixtab(q, P.ws_mixtab, s));
     for (int m = 0; m < n_moves; ++m) {
         q.m = m;
-        HIPCHK(launch_propose(N, P.K, P.active, P.slot, q, xi, P.ws_v, P.ws_logr, P.flags, s));
+        HIPCHK(launch_propose(N, P.K, P.active, P.slot, q, P.ws_mixtab, xi, P.ws_v, P.ws_logr, P.flags, s));
         Solve o;
         o.level = level;
         o.phi = P.ws_phinew;

@@ -12,6 +12,9 @@ constexpr int MAX_OBS = 64;
 constexpr int MAX_M = 16;
 constexpr int MAX_KR = 64;
 constexpr int GM_PAR = 2 * MAX_M + 4 * MAX_M * MAX_KR;   // doubles in one mixture-fit parameter block
+// Proposal table of one group's mixture: [MAX_M][MAX_KR] 1/s_ji, then [MAX_M] half the sum of
+// log s_ji over the active modes, then [MAX_M] the running sums of the weights.
+constexpr int MIXTAB = MAX_M * (MAX_KR + 2);
 constexpr int MAX_TERMS = 16;        // terms of an L^2 mixture likelihood
 constexpr int KIND_DARCY = 0;        // forward map: Darcy solve, observations at nodes
 constexpr int KIND_L2MIX = 1;        // no forward map: mixture likelihood in L^2 on the coefficients
@@ -60,6 +63,7 @@ struct Problem {
     double* ws_fit_par = nullptr;     // [2][GM_PAR]  EM parameter blocks (ping-pong)
     double* ws_fit_part = nullptr;    // [workgroups of 128 particles][MAX_M][1 + 2 MAX_KR]  partial sums
     int32_t* ws_fit_centers = nullptr;  // [MAX_M] seeded rows
+    double* ws_mixtab = nullptr;      // [MAX_LEVELS][MIXTAB]  mixture tables of the proposal, per group
     int n_cu = 0;                // compute units of the device
     int32_t* flags = nullptr;    // device status word
     unsigned long long* stats = nullptr;  // [4] iterations, sweeps, solves, preconditioner applications
@@ -242,8 +246,10 @@ hipError_t launch_prior(int64_t N, int K, uint64_t seed, uint64_t ctr, double* x
 hipError_t launch_potential(int64_t N, int n_obs, const double* G, const double* y, double inv2s2, double* phi,
                             hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_mixtab(const MoveParams& q, double* tab, hipStream_t s);
 hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
-                          const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s);
+                          const double* tab, const double* xi, double* v, double* logr, int32_t* flags,
+                          hipStream_t s);
 hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
                          const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s);
 hipError_t prepare_kernels();

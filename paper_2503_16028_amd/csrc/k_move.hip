@@ -86,13 +86,57 @@ __device__ __forceinline__ int choose_component(uint64_t seed, uint64_t ctr, int
 // a sum over the active modes only (g = gamma).  The first argument of alpha is where the
 // reverse move lands.  This is the ratio of the Gaussian components' Radon-Nikodym
 // derivatives of eq. (auv of pCN-GMM4) written out for diagonal covariances.
+//
+// Split as alpha_j(a, b) = (|d|^2 - sum_i (d_i - (1 - g) m_ji)^2 / s_ji) / (2 beta^2) - h_j with
+// d = a - g b over the active modes and h_j = sum_i log(s_ji) / 2: |d|^2 is one reduction for
+// every component, and 1/s_ji, h_j and the running weight sums that pick the component come from
+// a table built once per call (they depend on the mixture only).
+__global__ __launch_bounds__(64) void mixtab_kernel(MoveParams q, double* __restrict__ tab) {
+    const int g = blockIdx.x, lane = threadIdx.x, M = q.M, kr = q.kr;
+    const double* logw = q.logw + (int64_t)g * M;
+    const double* scale = q.scale + (int64_t)g * M * kr;
+    double* t = tab + (int64_t)g * MIXTAB;
+    for (int m = 0; m < M; ++m) {
+        double h = 0.0;
+        if (lane < kr) {
+            const double sv = scale[m * kr + lane];
+            t[m * MAX_KR + lane] = 1.0 / sv;
+            h = 0.5 * log(sv);
+        }
+        h = wave_sum(h);
+        if (lane == 0) t[MAX_M * MAX_KR + m] = h;
+    }
+    if (lane == 0) {   // the same running sum as choose_component, so the same component is picked
+        double cum = 0.0;
+        for (int m = 0; m < M; ++m) {
+            cum += exp(logw[m]);
+            t[MAX_M * MAX_KR + MAX_M + m] = cum;
+        }
+    }
+}
+
+hipError_t launch_mixtab(const MoveParams& q, double* tab, hipStream_t s) {
+    mixtab_kernel<<<dim3((unsigned)q.n_groups), dim3(64), 0, s>>>(q, tab);
+    return hipGetLastError();
+}
+
+// Log-sum-exp of each half of the wave, every lane of a half holding one value (-inf for none).
+__device__ __forceinline__ double half_lse(double x) {
+    double mx = x;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    double e = (x > -INFINITY) ? exp(x - mx) : 0.0;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    return mx + log(e);
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void propose_kernel(int K, const int32_t* __restrict__ active,
                                                       const int32_t* __restrict__ slot, MoveParams q,
+                                                      const double* __restrict__ tab,
                                                       const double* __restrict__ xi, double* __restrict__ v,
                                                       double* __restrict__ logr, int32_t* flags) {
-    __shared__ int comp;
-    __shared__ double fw[MAX_M], bw[MAX_M];
     const int64_t n = blockIdx.x;
     const int grp = mp_group(q, n);
     const double beta = grp >= 0 ? mp_beta(q, grp) : 0.0, tau = grp >= 0 ? mp_tau(q, grp) : 0.0;
@@ -110,11 +154,21 @@ __global__ __launch_bounds__(NT) void propose_kernel(int K, const int32_t* __res
     const double* logw = q.logw + (int64_t)grp * M;
     const double* mean = q.mean + (int64_t)grp * M * kr;
     const double* scale = q.scale + (int64_t)grp * M * kr;
+    const double* invs = tab + (int64_t)grp * MIXTAB;
+    const double* half_logs = invs + MAX_M * MAX_KR;
+    const double* cumw = half_logs + MAX_M;
     const uint64_t ctr = mp_ctr(q);
     const double gamma = sqrt(1.0 - beta * beta);
-    if (threadIdx.x == 0) comp = choose_component(q.seed, ctr, n, M, logw);
-    __syncthreads();
-    const int j = comp;
+    int j = M - 1;   // component: the first whose running weight sum exceeds U_comp (every lane alike)
+    {
+        const uint4 w = draw(q.seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const double uc = res53(w.x, w.y);
+        for (int m = 0; m < M; ++m)
+            if (cumw[m] > uc) {
+                j = m;
+                break;
+            }
+    }
     const int nb = (K + 1) / 2;
     for (int blk = threadIdx.x; blk < nb; blk += NT) {
         double z[2];
@@ -135,45 +189,44 @@ __global__ __launch_bounds__(NT) void propose_kernel(int K, const int32_t* __res
     __syncthreads();
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        const double inv2b2 = 0.5 / (beta * beta);
-        double a_x = 0.0, a_v = 0.0;
+        const double inv2b2 = 0.5 / (beta * beta), omg = 1.0 - gamma;
+        double d1 = 0.0, d2 = 0.0;   // reverse (xi - g v) and forward (v - g xi) displacements
         if (lane < kr) {
             const int k = active[lane];
-            a_x = xp[k];
-            a_v = vp[k];
+            const double a_x = xp[k], a_v = vp[k];
+            d1 = a_x - gamma * a_v;
+            d2 = a_v - gamma * a_x;
         }
+        const double nf = wave_sum(d1 * d1), nbk = wave_sum(d2 * d2);
+        double mine = -INFINITY;   // lane m: alpha_m(xi, v) + log w_m; lane 32 + m: alpha_m(v, xi) + log w_m
         for (int m = 0; m < M; ++m) {
-            double tf = 0.0, tb = 0.0;
+            double pf = 0.0, pb = 0.0;
             if (lane < kr) {
-                const double mm = (1.0 - gamma) * mean[m * kr + lane], s = scale[m * kr + lane];
-                const double d1 = a_x - gamma * a_v, d2 = a_v - gamma * a_x;   // reverse, forward
-                tf = d1 * d1 * inv2b2 - (d1 - mm) * (d1 - mm) * inv2b2 / s - 0.5 * log(s);
-                tb = d2 * d2 * inv2b2 - (d2 - mm) * (d2 - mm) * inv2b2 / s - 0.5 * log(s);
+                const double mm = omg * mean[m * kr + lane], is = invs[m * MAX_KR + lane];
+                const double e1 = d1 - mm, e2 = d2 - mm;
+                pf = e1 * e1 * is;
+                pb = e2 * e2 * is;
             }
-            tf = wave_sum(tf);
-            tb = wave_sum(tb);
-            if (lane == 0) {
-                fw[m] = logw[m] + tf;   // alpha_m(xi, v)
-                bw[m] = logw[m] + tb;   // alpha_m(v, xi)
-            }
+            pf = wave_sum(pf);
+            pb = wave_sum(pb);
+            const double lw = logw[m] - half_logs[m];
+            if (lane == m) mine = lw + (nf - pf) * inv2b2;
+            if (lane == 32 + m) mine = lw + (nbk - pb) * inv2b2;
         }
-        if (lane == 0) {
-            double mf = -INFINITY, mb = -INFINITY;
-            for (int m = 0; m < M; ++m) { mf = fmax(mf, fw[m]); mb = fmax(mb, bw[m]); }
-            double sf = 0.0, sb = 0.0;
-            for (int m = 0; m < M; ++m) { sf += exp(fw[m] - mf); sb += exp(bw[m] - mb); }
-            logr[n] = (mf + log(sf)) - (mb + log(sb));
-        }
+        const double lse = half_lse(mine);
+        const double lse_b = __shfl(lse, 32, 64);
+        if (lane == 0) logr[n] = lse - lse_b;
     }
 }
 
 hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
-                          const double* xi, double* v, double* logr, int32_t* flags, hipStream_t s) {
+                          const double* tab, const double* xi, double* v, double* logr, int32_t* flags,
+                          hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    if (K <= 128)   // one wave per particle when the draw is short (the log ratio needs one wave)
-        propose_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
+    if (K <= 128)
+        propose_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, active, slot, q, tab, xi, v, logr, flags);
     else
-        propose_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, xi, v, logr, flags);
+        propose_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, tab, xi, v, logr, flags);
     return hipGetLastError();
 }
 
