@@ -28,6 +28,8 @@
 // immediate offsets with no branches.  Dot products are wave butterflies plus a fixed-order sum
 // of the wave partials: every thread sees the same bits, and a particle's result does not depend
 // on the batch it is solved in.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace smc {
@@ -267,6 +269,8 @@ struct SolveShared {
 // call passes them as generic pointers).
 typedef const __attribute__((address_space(1))) double* gcdp;
 typedef __attribute__((address_space(1))) double* gdp;
+template <typename S> using gcp = const __attribute__((address_space(1))) S*;
+template <typename S> using gp = __attribute__((address_space(1))) S*;
 // Read-only data through the constant address space: wave-uniform loads of it become scalar loads
 // into SGPRs, which leaves the vector registers to the strip's own loads.  Only for arrays no
 // kernel writes while it runs (the coefficient field, written by the synthesis launch before).
@@ -311,9 +315,9 @@ __device__ __forceinline__ double from_prev_lane(double v, double edge) {
 // loads are issued 8 rows at a time.  The east and west values of e and x come from the adjacent
 // lanes; only the two wave edges load them (e, read-only here, through the scalar unit: in SGPRs
 // they leave the vector registers to the rows' loads).
-template <typename T, int NN, int R, bool SRC>
+template <typename T, int NN, int R, bool SRC, typename SD>
 __device__ __noinline__ double strip_residual(const double* __restrict__ e_, const double* __restrict__ xo_,
-                                              const double* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
+                                              const SD* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
                                               bool zero_x, double f, const double* __restrict__ src_w,
                                               const int* __restrict__ src_at, int n_obs) {
     static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
@@ -321,7 +325,7 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
     const double inv_h2 = (double)NN * (double)NN;
     gcdp e = (gcdp)e_;
     gcdp xo = (gcdp)xo_;
-    gcdp sd = (gcdp)sd_;
+    gcp<SD> sd = (gcp<SD>)sd_;
     __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
     const int i = c + 1;
     const bool colin = c < NN - 1;
@@ -332,7 +336,7 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
             const int g = g0 + r;
             const bool in = colin && g < NN - 1;
             const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
-            const double sdv = sd[g * NN + c];
+            const double sdv = (double)sd[g * NN + c];
             acc += in ? fr * fr : 0.0;
             tb[NN + 1 + r * NN] = in ? (T)(sdv * fr) : T(0);
         }
@@ -359,7 +363,7 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
             const int g = g0 + r0 + k, j = g + 1;
             eN[k] = e[min(j + 1, NN) * NP1 + i];
             xN[k] = xo[min(g + 1, NN - 1) * NN + c];
-            sdv[k] = sd[g * NN + c];
+            sdv[k] = (double)sd[g * NN + c];
             const int ju = g0u + r0 + k + 1;
             eEe[k] = eu[ju * NP1 + ieE];
             eWe[k] = eu[ju * NP1 + ieW];
@@ -391,10 +395,10 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
 }
 
 // x += D^{-1/2} y for the strip, y staged in its LDS slots (x = D^{-1/2} y when `first`).
-template <typename T, int NN, int R>
-__device__ __noinline__ void strip_update(double* xo_, const double* sd_, const T* tb_, int c, int g0, bool first) {
+template <typename T, int NN, int R, typename SD>
+__device__ __noinline__ void strip_update(double* xo_, const SD* sd_, const T* tb_, int c, int g0, bool first) {
     gdp xo = (gdp)xo_;
-    gcdp sd = (gcdp)sd_;
+    gcp<SD> sd = (gcp<SD>)sd_;
     const __attribute__((address_space(3))) T* tb = (const __attribute__((address_space(3))) T*)tb_;
     constexpr int B = R < 16 ? R : 16;   // rows whose loads are issued together
 #pragma unroll 1
@@ -403,7 +407,7 @@ __device__ __noinline__ void strip_update(double* xo_, const double* sd_, const 
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int g = g0 + r0 + k;
-            sdv[k] = sd[g * NN + c];
+            sdv[k] = (double)sd[g * NN + c];
             xv[k] = first ? 0.0 : xo[g * NN + c];
         }
 #pragma unroll
@@ -415,14 +419,14 @@ __device__ __noinline__ void strip_update(double* xo_, const double* sd_, const 
 }
 
 // D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots.
-template <typename T, int NN, int R>
-__device__ __noinline__ void strip_setup(const double* __restrict__ e_, double* __restrict__ sd_, T* __restrict__ tb_,
+template <typename T, int NN, int R, typename SD>
+__device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __restrict__ sd_, T* __restrict__ tb_,
                                          int c, int g0) {
     static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
     constexpr int NP1 = NN + 1;
     const double h = 1.0 / NN;
     gcdp e = (gcdp)e_;
-    gdp sd = (gdp)sd_;
+    gp<SD> sd = (gp<SD>)sd_;
     __attribute__((address_space(3))) T* tb = (__attribute__((address_space(3))) T*)tb_;
     const int i = c + 1;
     const int lane = threadIdx.x & 63;
@@ -447,7 +451,7 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, double* 
             const int r = r0 + k, g = g0 + r, j = g + 1;
             const bool in = c < NN - 1 && g < NN - 1;
             const double S = from_next_lane(eC, eEe[k]) + from_prev_lane(eC, eWe[k]) + eN[k] + eS;
-            sd[g * NN + c] = in ? h / sqrt(eC * S) : 1.0;
+            sd[g * NN + c] = in ? (SD)(h / sqrt(eC * S)) : SD(1);
             tb[NN + 1 + r * NN] = in ? (T)sqrt(eC / S) : T(0);
             eS = eC;
             eC = (j + 1 <= NN) ? eN[k] : 0.0;
@@ -481,7 +485,10 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     const int i = c + 1;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
-    double* sd = a.sd + row * a.sd_stride;
+    // D^{-1/2} is a scaling of the inner system, so with FP32 inner solves it is kept in FP32 (the
+    // update applies the same values the residual was scaled by); FP64 inner solves keep FP64.
+    using SD = typename std::conditional<std::is_same<T, float>::value, float, double>::type;
+    SD* sd = reinterpret_cast<SD*>(a.sd) + row * a.sd_stride;
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     // own node of row r: tb[NN + 1 + r * NN]; east +1, west -1, north +NN, south -NN
     T* tb = ly + PAD + b * R * NN + c - NN - 1;
@@ -492,7 +499,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     }
     // ---- setup: D^{-1/2} (FP64, workspace) and t (registers), staged through the thread's own LDS slots
     if constexpr (SPLIT) {
-        strip_setup<T, NN, R>(e, sd, tb, c, b * R);
+        strip_setup<T, NN, R, SD>(e, sd, tb, c, b * R);
     } else {
         // column i of e, rows j-1, j, j+1 carried along the strip (j = g + 1)
         double eS = e[(b * R) * NP1 + i], eC = e[(b * R + 1) * NP1 + i];
@@ -506,7 +513,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
                 sdv = h / sqrt(eC * S);
                 tv = sqrt(eC / S);
             }
-            sd[g * NN + c] = sdv;
+            sd[g * NN + c] = (SD)sdv;
             tb[NN + 1 + r * NN] = (T)tv;
             eS = eC;
             eC = eN;
@@ -592,7 +599,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
                     if (c < NN - 1 && g < NN - 1) {
                         const double f = rhs(g * NN + c);
                         acc += f * f;
-                        out = (T)(sd[g * NN + c] * f);
+                        out = (T)((double)sd[g * NN + c] * f);
                     }
                     tb[NN + 1 + r * NN] = out;
                 }
@@ -616,7 +623,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
                                                (e[j * NP1 + i + 1] * (xC - xE) + e[j * NP1 + i - 1] * (xC - xW) +
                                                 eN * (xC - xN) + eS * (xC - xS));
                         acc += res * res;
-                        out = (T)(sd[g * NN + c] * res);
+                        out = (T)((double)sd[g * NN + c] * res);
                     }
                     tb[NN + 1 + r * NN] = out;
                     eS = eC;
@@ -727,12 +734,12 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
 #pragma unroll
             for (int r = 0; r < R; ++r) tb[NN + 1 + r * NN] = x[r];
             if constexpr (SPLIT) {
-                strip_update<T, NN, R>(xo, sd, tb, c, b * R, sweep == 0);
+                strip_update<T, NN, R, SD>(xo, sd, tb, c, b * R, sweep == 0);
             } else {
 #pragma unroll 1
                 for (int r = 0; r < R; ++r) {
                     const int g = b * R + r;
-                    const double corr = sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
+                    const double corr = (double)sd[g * NN + c] * (double)tb[NN + 1 + r * NN];
                     xo[g * NN + c] = (sweep == 0) ? corr : xo[g * NN + c] + corr;
                 }
             }
