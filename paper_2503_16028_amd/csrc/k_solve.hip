@@ -451,8 +451,9 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __re
             const int r = r0 + k, g = g0 + r, j = g + 1;
             const bool in = c < NN - 1 && g < NN - 1;
             const double S = from_next_lane(eC, eEe[k]) + from_prev_lane(eC, eWe[k]) + eN[k] + eS;
-            sd[g * NN + c] = in ? (SD)(h / sqrt(eC * S)) : SD(1);
-            tb[NN + 1 + r * NN] = in ? (T)sqrt(eC / S) : T(0);
+            const double rs = 1.0 / sqrt(eC * S);   // h / sqrt(eC S) and sqrt(eC / S) from one root
+            sd[g * NN + c] = in ? (SD)(h * rs) : SD(1);
+            tb[NN + 1 + r * NN] = in ? (T)(eC * rs) : T(0);
             eS = eC;
             eC = (j + 1 <= NN) ? eN[k] : 0.0;
         }
@@ -510,8 +511,9 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
             double sdv = 1.0, tv = 0.0;
             if (c < NN - 1 && g < NN - 1) {
                 const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + eN + eS;
-                sdv = h / sqrt(eC * S);
-                tv = sqrt(eC / S);
+                const double rs = 1.0 / sqrt(eC * S);   // h / sqrt(eC S) and sqrt(eC / S) from one root
+                sdv = h * rs;
+                tv = eC * rs;
             }
             sd[g * NN + c] = (SD)sdv;
             tb[NN + 1 + r * NN] = (T)tv;
@@ -944,8 +946,9 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
         if (interior(g, c)) {
             const double eP = e[j * NP1 + i];
             const double S = e[j * NP1 + i + 1] + e[j * NP1 + i - 1] + e[(j + 1) * NP1 + i] + e[(j - 1) * NP1 + i];
-            sdv = h / sqrt(eP * S);
-            tt = sqrt(eP / S);
+            const double rs = 1.0 / sqrt(eP * S);   // h / sqrt(eP S) and sqrt(eP / S) from one root
+            sdv = h * rs;
+            tt = eP * rs;
         }
         sd[k] = sdv;
         tv[k] = (T)tt;
