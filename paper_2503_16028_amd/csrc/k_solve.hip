@@ -488,8 +488,10 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     double* x64 = a.x64 + row * a.x_stride;
     // D^{-1/2} is a scaling of the inner system, so with FP32 inner solves it is kept in FP32 (the
     // update applies the same values the residual was scaled by); FP64 inner solves keep FP64.
+    // Either way it starts at the particle's own FP64 row: a mixed-grid launch keeps FP64 rows for
+    // the global-memory solver in the same workspace.
     using SD = typename std::conditional<std::is_same<T, float>::value, float, double>::type;
-    SD* sd = reinterpret_cast<SD*>(a.sd) + row * a.sd_stride;
+    SD* sd = reinterpret_cast<SD*>(a.sd + row * a.sd_stride);
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     // own node of row r: tb[NN + 1 + r * NN]; east +1, west -1, north +NN, south -NN
     T* tb = ly + PAD + b * R * NN + c - NN - 1;

@@ -89,6 +89,36 @@ def test_forward_levels(prec_name):
         assert np.array_equal(G1.cpu().numpy(), got[rows]), lv
 
 
+@pytest.mark.parametrize("levels", [[2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1], [0, 1, 2, 0, 1, 2]])
+def test_forward_levels_rows_keep_their_workspace(levels):
+    """Rows of every grid in one launch, the 256^2 rows first: the FP32 scaling of an on-chip
+    (64^2, 128^2) row lies inside its own row of the workspace, never inside the FP64 scaling
+    of a 256^2 row solved at the same time.  Every row converges and equals, bit for bit, a
+    launch of its grid alone."""
+    from paper_2503_16028_amd import smc
+    lv = np.array(levels, dtype=np.int32)
+    banner("forward levels rows keep their workspace", levels)
+    d, op = load("c5")
+    N = len(lv)
+    p = mixed_problem(d, N, "fp32_refine")
+    xi = inputs.particles(N, op.K, 50)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, t(xi), t(lv, torch.int32), smc.SMC_FP32_REFINE, G, it)
+    torch.cuda.synchronize()
+    assert (it.cpu().numpy() > 0).all(), it.cpu().numpy()
+    assert smc.smc_status_flags(p) == 0
+    got = G.cpu().numpy()
+    for l in sorted(set(levels)):
+        rows = np.nonzero(lv == l)[0]
+        q = smc.Problem(d, len(rows), grids=GRIDS, tol64=1e-10, tol_inner=1e-5, max_iter=80 * 256)
+        G1 = torch.empty(len(rows), op.n_obs, dtype=torch.float64, device=DEV)
+        smc.smc_forward_batch(q, len(rows), t(xi[rows]), t(np.full(len(rows), l, np.int32), torch.int32),
+                              smc.SMC_FP32_REFINE, G1)
+        torch.cuda.synchronize()
+        assert np.array_equal(G1.cpu().numpy(), got[rows]), l
+
+
 def p_tol(prec_name):
     return 6e-12 if prec_name == "fp64" else 1e-10
 
