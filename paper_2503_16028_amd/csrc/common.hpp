@@ -53,7 +53,8 @@ struct Problem {
     double* ws_x64 = nullptr;    // [n_max][n_big^dim]      FP64 solution
     double* ws_lam = nullptr;    // [n_max][n_big^2]        FP64 adjoint solution (2D)
     double* ws_gnew = nullptr;   // [n_max][K]              gradient at the proposal (2D)
-    double* ws_sd = nullptr;     // [n_max][n_big^2]        D^{-1/2} of the Jacobi scaling
+    double* ws_sd = nullptr;     // [n_max][n_big^2]        D^{-1/2} of the Jacobi scaling (FP32 in the first
+                                 //                         half of a row for FP32 on-chip solves)
     void* ws_vec = nullptr;      // [n_max][6][n_big^2] doubles: vectors of the global-memory solver
     double* ws_G = nullptr;      // [n_max][n_obs]
     int32_t* ws_iters = nullptr; // [n_max]
@@ -147,7 +148,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 struct SolveArgs {
     const double* e;     // exp(u/2) nodal, row stride e_stride
     double* x64;         // FP64 solution, row stride x_stride
-    double* sd;          // D^{-1/2}, row stride x_stride
+    double* sd;          // D^{-1/2}, row stride x_stride (doubles; an FP32 row starts at the same place)
     void* vec;           // global-solver vectors, row stride vec_stride (doubles)
     int64_t e_stride, x_stride, sd_stride, vec_stride;
     double* lam;         // adjoint solution [N][lam_stride] (interior layout as x64), or null: no adjoint

@@ -500,7 +500,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
         ly[k] = T(0);
         ly[PAD + NN * NN + k] = T(0);
     }
-    // ---- setup: D^{-1/2} (FP64, workspace) and t (registers), staged through the thread's own LDS slots
+    // ---- setup: D^{-1/2} (workspace, in SD) and t (registers), staged through the thread's own LDS slots
     if constexpr (SPLIT) {
         strip_setup<T, NN, R, SD>(e, sd, tb, c, b * R);
     } else {
