@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--moves", type=int, default=N_MOVES, help="moves per stage (profiling runs use fewer)")
     ap.add_argument("--tile", type=int, default=0,
                     help="rows per thread of the 128^2 solver (0: autotune before timing)")
+    ap.add_argument("--precond", choices=["auto", "jacobi"], default="auto",
+                    help="preconditioner of the solves (jacobi: the Jacobi-scaled CG alone, a comparison point)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB device-to-device, to calibrate memory-traffic counters")
     args = ap.parse_args()
@@ -239,9 +241,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    fast_poisson = args.precond == "auto"
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3,
+                    precond=smc.PRECOND_AUTO if fast_poisson else smc.PRECOND_JACOBI)
     unknowns = (GRID - 1) ** 2
-    if args.tile:
+    if not fast_poisson:
+        tile, tile_ms = 16, {}   # the Jacobi-only 128^2 solver has one shape, 16 rows per thread
+    elif args.tile:
         smc.smc_set_tile(p, 0, args.tile)
         tile, tile_ms = args.tile, {}
     else:
@@ -346,12 +352,16 @@ def main():
         "config": {"workload": "2D Darcy 128x128, N=4096 particles, 8-component GM-pCN over 64 active modes, "
                                "20 moves per tempering stage, 10 mirrored observations",
                    "grid": GRID, "particles": N, "mixture": M, "moves_per_stage": args.moves,
-                   "solver": "Jacobi-scaled CG in FP32, fast-Poisson (FP16 MFMA sine transform) preconditioner, "
-                             "inside FP64 residual refinement to 1e-10"},
+                   "solver": ("Jacobi-scaled CG in FP32, fast-Poisson (FP16 MFMA sine transform) preconditioner, "
+                              "inside FP64 residual refinement to 1e-10") if fast_poisson else
+                             "Jacobi-scaled CG in FP32 (no further preconditioner), inside FP64 residual refinement "
+                             "to 1e-10"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / F16_MFMA_PEAK, "traffic": measured_traffic(tile),
+                     "unit": "TFLOP/s", "frac": achieved / F16_MFMA_PEAK,
+                     "traffic": measured_traffic(tile) if fast_poisson else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "cg_onchip<float,128,%d,fast-Poisson>" % tile, "kernel_ms_per_launch": kernel_ms,
+                     "kernel": "cg_onchip<float,128,%d,%s>" % (tile, "fast-Poisson" if fast_poisson else "Jacobi"),
+                     "kernel_ms_per_launch": kernel_ms,
                      "valu_tflops": valu_flops / (prof32["ms"] * 1e-3) / 1e12,
                      "cg_iters_per_solve": prof32["iters"] / max(1, prof32["solves"]),
                      "precond_apps_per_solve": prof32["precond_apps"] / max(1, prof32["solves"]),
