@@ -305,6 +305,8 @@ def _move_case(name, grid, N, M, beta, tau, n_moves, prec, seed):
     ("t2", 32, 16, 4, 1.0, 0.5, 2),       # beta = 1: mixture independence sampler
     ("t1", 64, 50, 0, 0.3, 1.0, 4),       # 1D pCN (the 1D workload's kernel)
     ("c2", 64, 6, 4, 0.2, 0.6, 2),
+    ("t2", 32, 20, 16, 0.4, 0.7, 2),      # the most components: every lane of each half-wave sum
+    ("t2", 16, 20, 1, 0.6, 0.8, 2),       # one component
 ])
 def test_move_fp64(name, grid, N, M, beta, tau, n_moves):
     banner("move fp64", name, grid, N, M, beta, tau, n_moves)
