@@ -23,6 +23,7 @@ FLOPS_PER_UNKNOWN_ITER = 18     # one scaled-CG iteration per interior unknown, 
 FLOPS_PER_UNKNOWN_SWEEP = 16    # one FP64 residual evaluation per interior unknown
 FP32_VECTOR_PEAK = 157.3e12     # MI355X published FP32 vector peak
 F16_MFMA_PEAK = 2.5e15          # MI355X published dense fp16 and bf16 matrix peak
+HBM_PEAK = 8.0e12               # MI355X HBM3E peak, bytes/s
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "cg_onchip_128x32_fastpoisson_c3_counters.md")
@@ -336,6 +337,7 @@ def main():
         variants["fp64_per_particle_moves_per_s"] = done * nm / (time.perf_counter() - t0)
         variants["fp64_per_particle_sample"] = "%d particles x %d move, one launch sequence per particle" % (done, nm)
         variants["fp32_refine_batched_moves_per_s"] = value
+    traffic = measured_traffic(tile) if fast_poisson else None
     out = {
         "metric": "particle GM-pCN moves/sec (solve+Phi) at 128^2, N=4096; FP32+refine vs FP64",
         "value": value,
@@ -358,7 +360,9 @@ def main():
                              "to 1e-10"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / F16_MFMA_PEAK,
-                     "traffic": measured_traffic(tile) if fast_poisson else None,
+                     "traffic": traffic,
+                     "traffic_tb_s": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e12,
+                     "traffic_frac_of_hbm_peak": None if traffic is None else traffic / (kernel_ms * 1e-3) / HBM_PEAK,
                      "traffic_unit": "bytes per launch",
                      "kernel": "cg_onchip<float,128,%d,%s>" % (tile, "fast-Poisson" if fast_poisson else "Jacobi"),
                      "kernel_ms_per_launch": kernel_ms,
