@@ -12,6 +12,12 @@ namespace smc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Waves of a 2D synthesis workgroup: the kernel alternates matrix-core, exponential and store
+// phases and is bound by their latency, so eight waves share one workgroup's LDS (three
+// workgroups, 24 waves, per compute unit at 128^2).
+constexpr int SYN_WAVES = 8;
+constexpr int SYN_THREADS = 64 * SYN_WAVES;
+
 // MFMA f64 16x16x4 operand layout (one double per lane), checked on the device:
 //   A[16][4]: lane = row + 16 * k     B[4][16]: lane = col + 16 * k
 //   D[16][16]: lane = col + 16 * (row % 4), element row / 4
@@ -26,7 +32,7 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
     double* X = smem;                           // [KLP][LD]
     double* T = X + KLP * LD;                   // [KLP][npad]
 
-    for (int t = threadIdx.x; t < KLP * KLP; t += 256) {
+    for (int t = threadIdx.x; t < KLP * KLP; t += SYN_THREADS) {
         const int k = t / KLP, l = t % KLP;
         X[k * LD + l] = (k < kl && l < kl) ? sqrt_lam[k * kl + l] * xp[k * kl + l] : 0.0;
     }
@@ -45,8 +51,8 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
             b[s2] = r < np1 ? v : 0.0;
         }
     };
-    // T[k][j] = sum_l X[k][l] B[j][l]; a wave takes node blocks jb = wave, wave + 4, ...
-    for (int jb = wave; jb < ntj; jb += 4) {
+    // T[k][j] = sum_l X[k][l] B[j][l]; a wave takes node blocks jb = wave, wave + SYN_WAVES, ...
+    for (int jb = wave; jb < ntj; jb += SYN_WAVES) {
         double b[KS];
         bfrag(16 * jb, b);
 #pragma unroll
@@ -62,7 +68,7 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
     __syncthreads();
     // U[j][i] = sum_k T[k][j] B[i][k]; a wave keeps the B operand of its column block ib and
     // sweeps the row blocks
-    for (int ib = wave; ib < ntj; ib += 4) {
+    for (int ib = wave; ib < ntj; ib += SYN_WAVES) {
         double b[KS];
         bfrag(16 * ib, b);
         const int i = 16 * ib + lr;
@@ -81,7 +87,7 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
 }
 
 template <bool EXPHALF>
-__global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__ xi, int K, int kl,
+__global__ __launch_bounds__(SYN_THREADS) void synth2d_kernel(const double* __restrict__ xi, int K, int kl,
                                                       const double* __restrict__ sqrt_lam,
                                                       const double* __restrict__ basis, int n,
                                                       double* __restrict__ out, int64_t out_stride) {
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(256) void synth2d_kernel(const double* __restrict__
 
 // The same for particles on several grids: particle p on grid level[p] (others are skipped).
 template <bool EXPHALF>
-__global__ __launch_bounds__(256) void synth2d_levels_kernel(const double* __restrict__ xi, int K, int kl,
+__global__ __launch_bounds__(SYN_THREADS) void synth2d_levels_kernel(const double* __restrict__ xi, int K, int kl,
                                                              const double* __restrict__ sqrt_lam, LevelTable lt,
                                                              const int32_t* __restrict__ level,
                                                              double* __restrict__ out, int64_t out_stride) {
@@ -220,9 +226,9 @@ hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_la
     const int npad = (n + 1 + 15) & ~15;
     const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
     if (exp_half)
-        synth2d_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
+        synth2d_kernel<true><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
     else
-        synth2d_kernel<false><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
+        synth2d_kernel<false><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
     return hipGetLastError();
 }
 
@@ -235,10 +241,10 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
     const int npad = (nmax + 1 + 15) & ~15;
     const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
     if (exp_half)
-        synth2d_levels_kernel<true><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
+        synth2d_levels_kernel<true><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
                                                                              out_stride);
     else
-        synth2d_levels_kernel<false><<<dim3((unsigned)N), dim3(256), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
+        synth2d_levels_kernel<false><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
                                                                               out_stride);
     return hipGetLastError();
 }
