@@ -6,18 +6,19 @@
 
 namespace smc {
 
-// One wave per particle (four per workgroup); lanes stride over the modes.
+// Sixteen lanes per particle (four particles per wave, sixteen per workgroup); the lanes of a
+// particle stride over the modes and each likelihood term is summed by one 16-lane butterfly.
 __global__ __launch_bounds__(256) void l2mix_phi_kernel(int64_t N, int K, const double* __restrict__ sqrt_lam,
                                                         const double* __restrict__ c, int T, double inv2s2,
                                                         const double* __restrict__ xi, double* __restrict__ phi,
                                                         int32_t* __restrict__ iters) {
-    const int lane = threadIdx.x & 63;
-    const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (n >= N) return;   // uniform over the wave; there is no barrier below
+    const int sub = threadIdx.x & 15;
+    const int64_t n = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (n >= N) return;   // the same for all 16 lanes of a particle; the butterflies stay inside them
     double acc[MAX_TERMS];
 #pragma unroll
     for (int i = 0; i < MAX_TERMS; ++i) acc[i] = 0.0;
-    for (int k = lane; k < K; k += 64) {
+    for (int k = sub; k < K; k += 16) {
         const double a = sqrt_lam[k] * xi[n * K + k];
 #pragma unroll
         for (int i = 0; i < MAX_TERMS; ++i) {
@@ -32,7 +33,10 @@ __global__ __launch_bounds__(256) void l2mix_phi_kernel(int64_t N, int K, const 
 #pragma unroll
     for (int i = 0; i < MAX_TERMS; ++i) {
         if (i < T) {
-            ll[i] = -wave_sum(acc[i]) * inv2s2;
+            double v = acc[i];
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+            ll[i] = -v * inv2s2;
             mx = fmax(mx, ll[i]);
         }
     }
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(256) void l2mix_phi_kernel(int64_t N, int K, const 
 #pragma unroll
     for (int i = 0; i < MAX_TERMS; ++i)
         if (i < T) se += exp(ll[i] - mx);
-    if (lane == 0) {
+    if (sub == 0) {
         phi[n] = -(mx + log(se));
         if (iters) iters[n] = 0;
     }
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(256) void l2mix_phi_kernel(int64_t N, int K, const 
 hipError_t launch_l2mix_phi(int64_t N, int K, const double* sqrt_lam, const double* c, int T, double inv2s2,
                             const double* xi, double* phi, int32_t* iters, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    l2mix_phi_kernel<<<dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s>>>(N, K, sqrt_lam, c, T, inv2s2, xi, phi,
+    l2mix_phi_kernel<<<dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s>>>(N, K, sqrt_lam, c, T, inv2s2, xi, phi,
                                                                           iters);
     return hipGetLastError();
 }
