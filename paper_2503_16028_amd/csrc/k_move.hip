@@ -219,12 +219,135 @@ __global__ __launch_bounds__(NT) void propose_kernel(int K, const int32_t* __res
     }
 }
 
+// Log-sum-exp over a particle's 16 lanes, each holding one value (-inf for none).
+__device__ __forceinline__ double lse16(double x) {
+    double mx = x;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 16));
+    double e = (x > -INFINITY) ? exp(x - mx) : 0.0;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) e += __shfl_xor(e, off, 16);
+    return mx + log(e);
+}
+
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+    return v;
+}
+
+// The same proposal for K <= 128 modes: sixteen lanes per particle (four particles per wave,
+// sixteen per workgroup); a lane draws normal blocks sub, sub + 16, ... and holds the active
+// slots sub, sub + 16, ... (at most four), so each component's two sums are 16-lane butterflies.
+constexpr int P16_SLOTS = MAX_KR / 16;
+__global__ __launch_bounds__(256) void propose16_kernel(int64_t N, int K, const int32_t* __restrict__ active,
+                                                        const int32_t* __restrict__ slot, MoveParams q,
+                                                        const double* __restrict__ tab,
+                                                        const double* __restrict__ xi, double* __restrict__ v,
+                                                        double* __restrict__ logr, int32_t* flags) {
+    const int sub = threadIdx.x & 15;
+    const int64_t n = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = n < N;
+    const int grp = live ? mp_group(q, n) : -1;
+    const double beta = grp >= 0 ? mp_beta(q, grp) : 0.0, tau = grp >= 0 ? mp_tau(q, grp) : 0.0;
+    const bool valid = grp >= 0 && mp_valid(beta, tau);
+    const double* xp = xi + (live ? n : 0) * K;
+    double* vp = v + (live ? n : 0) * K;
+    const int M = q.M, kr = q.kr;
+    const double gamma = valid ? sqrt(1.0 - beta * beta) : 0.0;
+    const double* logw = q.logw + (int64_t)(grp >= 0 ? grp : 0) * M;
+    const double* mean = q.mean + (int64_t)(grp >= 0 ? grp : 0) * M * kr;
+    const double* scale = q.scale + (int64_t)(grp >= 0 ? grp : 0) * M * kr;
+    const double* invs = tab + (int64_t)(grp >= 0 ? grp : 0) * MIXTAB;
+    const double* half_logs = invs + MAX_M * MAX_KR;
+    const double* cumw = half_logs + MAX_M;
+    const uint64_t ctr = mp_ctr(q);
+    if (live && !valid) {   // no valid parameters: propose the current state, reject it
+        for (int k = sub; k < K; k += 16) vp[k] = xp[k];
+        if (sub == 0) {
+            logr[n] = -INFINITY;
+            if (grp >= 0 && flags) atomicOr(flags, SMC_FLAG_BADPARAM);
+        }
+    }
+    if (valid) {
+        int j = M - 1;   // component: the first whose running weight sum exceeds U_comp
+        const uint4 w = draw(q.seed, ctr, UNIFORM_BLOCK, (uint32_t)n);
+        const double uc = res53(w.x, w.y);
+        for (int m = 0; m < M; ++m)
+            if (cumw[m] > uc) {
+                j = m;
+                break;
+            }
+        const int nb = (K + 1) / 2;
+        for (int blk = sub; blk < nb; blk += 16) {
+            double z[2];
+            box_muller(draw(q.seed, ctr, (uint32_t)blk, (uint32_t)n), z[0], z[1]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = 2 * blk + h;
+                if (k >= K) break;
+                const int sl = slot[k];
+                double val = gamma * xp[k] + beta * z[h];
+                if (sl >= 0) {
+                    const double mj = mean[j * kr + sl], sj = scale[j * kr + sl];
+                    val = gamma * xp[k] + (1.0 - gamma) * mj + beta * sqrt(sj) * z[h];
+                }
+                vp[k] = val;
+            }
+        }
+    }
+    __syncthreads();   // every thread reaches it; the proposals are read back by the particle's lanes
+    if (!valid) return;
+    const double inv2b2 = 0.5 / (beta * beta), omg = 1.0 - gamma;
+    double d1[P16_SLOTS], d2[P16_SLOTS];   // reverse (xi - g v) and forward (v - g xi) displacements
+    double pnf = 0.0, pnb = 0.0;
+#pragma unroll
+    for (int s = 0; s < P16_SLOTS; ++s) {
+        const int i = sub + 16 * s;
+        d1[s] = 0.0;
+        d2[s] = 0.0;
+        if (i < kr) {
+            const int k = active[i];
+            const double a_x = xp[k], a_v = vp[k];
+            d1[s] = a_x - gamma * a_v;
+            d2[s] = a_v - gamma * a_x;
+        }
+        pnf += d1[s] * d1[s];
+        pnb += d2[s] * d2[s];
+    }
+    const double nf = sum16(pnf), nbk = sum16(pnb);
+    double mf = -INFINITY, mb = -INFINITY;   // lane m: log w_m + alpha_m(xi, v), log w_m + alpha_m(v, xi)
+    for (int m = 0; m < M; ++m) {
+        double pf = 0.0, pb = 0.0;
+#pragma unroll
+        for (int s = 0; s < P16_SLOTS; ++s) {
+            const int i = sub + 16 * s;
+            if (i < kr) {
+                const double mm = omg * mean[m * kr + i], is = invs[m * MAX_KR + i];
+                const double e1 = d1[s] - mm, e2 = d2[s] - mm;
+                pf += e1 * e1 * is;
+                pb += e2 * e2 * is;
+            }
+        }
+        pf = sum16(pf);
+        pb = sum16(pb);
+        if (sub == m) {
+            const double lw = logw[m] - half_logs[m];
+            mf = lw + (nf - pf) * inv2b2;
+            mb = lw + (nbk - pb) * inv2b2;
+        }
+    }
+    const double lf = lse16(mf), lb = lse16(mb);
+    if (sub == 0) logr[n] = lf - lb;
+}
+
 hipError_t launch_propose(int64_t N, int K, const int32_t* active, const int32_t* slot, const MoveParams& q,
                           const double* tab, const double* xi, double* v, double* logr, int32_t* flags,
                           hipStream_t s) {
     if (N <= 0) return hipSuccess;
     if (K <= 128)
-        propose_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, active, slot, q, tab, xi, v, logr, flags);
+        propose16_kernel<<<dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s>>>(N, K, active, slot, q, tab, xi, v, logr,
+                                                                               flags);
     else
         propose_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, active, slot, q, tab, xi, v, logr, flags);
     return hipGetLastError();
