@@ -423,11 +423,37 @@ __global__ __launch_bounds__(NT) void accept_kernel(int K, MoveParams q, const d
     }
 }
 
+// The same decision for K <= 128 modes, sixteen lanes per particle: every lane takes the same
+// decision from the same uniform and copies every sixteenth mode of an accepted proposal.
+__global__ __launch_bounds__(256) void accept16_kernel(int64_t N, int K, MoveParams q, const double* __restrict__ v,
+                                                       const double* __restrict__ logr,
+                                                       const double* __restrict__ phinew, double* __restrict__ xi,
+                                                       double* __restrict__ phi, int32_t* __restrict__ n_acc) {
+    const int sub = threadIdx.x & 15;
+    const int64_t n = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (n >= N) return;
+    const int grp = mp_group(q, n);
+    const uint4 w = draw(q.seed, mp_ctr(q), UNIFORM_BLOCK, (uint32_t)n);
+    const double ua = res53(w.z, w.w);
+    const double pn = phinew[n], lr = logr[n];
+    bool ok = false;
+    if (grp >= 0 && isfinite(pn) && lr > -INFINITY) {
+        const double la = fmin(0.0, mp_tau(q, grp) * (phi[n] - pn) + lr);
+        ok = log(ua) < la;
+    }
+    if (!ok) return;
+    for (int k = sub; k < K; k += 16) xi[n * K + k] = v[n * K + k];
+    if (sub == 0) {
+        phi[n] = pn;
+        n_acc[n] += 1;
+    }
+}
+
 hipError_t launch_accept(int64_t N, int K, const MoveParams& q, const double* v, const double* logr,
                          const double* phinew, double* xi, double* phi, int32_t* n_acc, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     if (K <= 128)
-        accept_kernel<64><<<dim3((unsigned)N), dim3(64), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
+        accept16_kernel<<<dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s>>>(N, K, q, v, logr, phinew, xi, phi, n_acc);
     else
         accept_kernel<256><<<dim3((unsigned)N), dim3(256), 0, s>>>(K, q, v, logr, phinew, xi, phi, n_acc);
     return hipGetLastError();
