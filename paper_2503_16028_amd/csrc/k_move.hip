@@ -1,5 +1,7 @@
-// Particle-level kernels of the move stage: prior draw, potential, pCN-GM proposal with its
-// acceptance ratio, Metropolis accept/reject and the row gather after resampling.
+// Particle-level kernels of the move stage: prior draw, potential, the proposal's mixture table,
+// pCN-GM proposal with its acceptance ratio, Metropolis accept/reject (one workgroup per particle
+// above 128 modes, sixteen lanes per particle up to 128), the mixture draw of SMC-GM, and the
+// pCN-Langevin proposal and decision, and the row gather after resampling.
 #include "common.hpp"
 
 namespace smc {
