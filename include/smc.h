@@ -304,17 +304,21 @@ int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M, int32_t it
  * W_n ∝ exp(-h Phi_n): the largest h (to a relative 2^-52, or (1 - tau) 2^-64) whose ESS still
  * passes, found by safeguarded Newton steps on log ESS; take h = 1 - tau when that already passes.
  * Outputs (device): *h, *tau_new (= 1 exactly on the last stage), W[N] normalised weights,
- * *log_z_inc = log((1/N) sum exp(-h Phi)).  Non-finite Phi get weight 0.  A zero step sets
- * SMC_FLAG_STALL and no finite potential sets SMC_FLAG_NONFINITE in *flags (device, may be
- * NULL), which is or-ed, never cleared.  N <= 1048576. */
+ * *log_z_inc = log((1/N) sum exp(-h Phi)).  Non-finite Phi get weight 0.  A zero step while
+ * tau < 1 sets SMC_FLAG_STALL (at tau = 1 the step is 0 and *tau_new = 1 without a flag), and
+ * no finite potential sets SMC_FLAG_NONFINITE in *flags (device, may be NULL), which is or-ed,
+ * never cleared.  N <= 1048576. */
 int smc_temper(int64_t N, const double* phi, const double* tau_in, double ess_frac, double* h,
                double* tau_new, double* W, double* log_z_inc, int32_t* flags, smc_stream stream);
 
 /* Systematic resampling (Alg. 1, resampling step) on an exact integer CDF:
  *   q_n = floor(W_n 2^53), C_n = q_0 + ... + q_n, Q = C_{N-1},
  *   idx_i = min{n : C_n > floor((i 2^53 + u53) Q / (N 2^53))},  i = 0..N-1.
- * u53 in [0, 2^53) is the uniform times 2^53.  idx[N] out (nondecreasing).  All-zero weights
- * set SMC_FLAG_BADWEIGHTS in *flags (device, may be NULL) and give idx = 0..N-1.
+ * u53 in [0, 2^53) is the uniform times 2^53.  idx[N] out (nondecreasing).
+ * W must be normalised, as smc_temper writes it: every W_n finite and in [0, 1], and
+ * sum W <= 1 + 2N 2^-53 (rounding of an FP64 normalisation), so that Q <= 2^53 + 2N.  Weights
+ * that break this (a W_n > 1, negative or NaN, or a total above that bound), and all-zero
+ * weights, set SMC_FLAG_BADWEIGHTS in *flags (device, may be NULL) and give idx = 0..N-1.
  * 1 <= N <= 2^24. */
 int smc_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags,
                  smc_stream stream);

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(TB) void temper_kernel(int64_t N, const double* __r
         *h_out = h;
         *tau_out = last ? 1.0 : tau + h;
         *log_z = -h * pmin + ls1 - log((double)N);
-        if (h == 0.0 && flags) atomicOr(flags, SMC_FLAG_STALL);
+        if (h == 0.0 && rest > 0.0 && flags) atomicOr(flags, SMC_FLAG_STALL);   // tau = 1: nothing left
     }
 }
 
@@ -186,9 +186,16 @@ hipError_t launch_temper(int64_t N, const double* phi, const double* tau_in, dou
 // particles: their integer weights are summed, the thread totals scanned, and a second pass
 // writes each particle's range.  Integer sums make the result independent of summation order,
 // and no CDF is stored, so N is limited only by the 32-bit output indices.
-__device__ __forceinline__ uint64_t qweight53(double w) {
-    return (w > 0.0 && w <= 1.0) ? (uint64_t)(w * 9007199254740992.0) : 0ull;
-}
+//
+// The weights must be normalised: each W_n in [0, 1] and finite, and their sum at most
+// 1 + 2N 2^-53 (the rounding of a normalisation in FP64), so that every q_n <= 2^53 and
+// Q <= QMAX = 2^53 + 2N.  A thread stops adding once its total passes QMAX (one more addend of
+// at most 2^53 cannot overflow 64 bits), and the scan adds at most TB totals of at most
+// QMAX + 2^53 < 2^55 each.  Any weight outside [0, 1] (NaN included) or Q > QMAX sets
+// SMC_FLAG_BADWEIGHTS and gives idx = 0..N-1, as do all-zero weights.
+__device__ __forceinline__ bool weight_ok(double w) { return w >= 0.0 && w <= 1.0; }   // false for NaN
+
+__device__ __forceinline__ uint64_t qweight53(double w) { return (uint64_t)(w * 9007199254740992.0); }
 
 // min{i >= 0 : (i 2^53 + u53) Q >= C N 2^53} = q + [r 2^53 > u53 Q], where C N = q Q + r
 // (0 <= r < Q); q <= N, found from a double estimate and corrected exactly.
@@ -205,11 +212,22 @@ __device__ __forceinline__ int64_t first_output(uint64_t C, int64_t N, uint64_t 
 __global__ __launch_bounds__(TB) void resample_kernel(int64_t N, const double* __restrict__ W, uint64_t u53,
                                                       int32_t* __restrict__ idx, int32_t* __restrict__ flags) {
     __shared__ uint64_t part[TB];
+    __shared__ int bad;
     const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
     const int64_t per = (N + TB - 1) / TB;
     const int64_t beg = tid * per, end = beg + per < N ? beg + per : N;
+    const uint64_t qmax = (1ull << 53) + 2ull * (uint64_t)N;
     uint64_t run = 0;
-    for (int64_t n = beg; n < end; ++n) run += qweight53(W[n]);
+    bool ok = true;
+    for (int64_t n = beg; n < end && ok; ++n) {
+        const double w = W[n];
+        ok = weight_ok(w);
+        if (ok) run += qweight53(w);
+        ok = ok && run <= qmax;
+    }
+    if (!ok) bad = 1;
     part[tid] = run;
     __syncthreads();
     // inclusive scan of the per-thread totals (Hillis-Steele on TB entries)
@@ -220,7 +238,7 @@ __global__ __launch_bounds__(TB) void resample_kernel(int64_t N, const double* _
         __syncthreads();
     }
     const uint64_t Q = part[TB - 1];
-    if (Q == 0) {
+    if (__builtin_amdgcn_readfirstlane(bad) || Q == 0 || Q > qmax) {
         for (int64_t i = tid; i < N; i += TB) idx[i] = (int32_t)i;
         if (tid == 0 && flags) atomicOr(flags, SMC_FLAG_BADWEIGHTS);
         return;

@@ -90,6 +90,7 @@ class SMCSampler:
         self.phi, self.phi2 = self.phi2, self.phi
         self.tau.copy_(self.tau_new)
         tau = float(self.tau.item())
+        self._check_step(tau)
         gm = self.mixture()
         smc.smc_gmpcn_move(p, N, gm, self.beta, tau, self.n_moves, self.seed, base, None, self.prec, self.xi,
                            self.phi, self.n_acc)
@@ -101,6 +102,12 @@ class SMCSampler:
         elif rate < 0.15:
             self.beta *= 0.5
         return tau
+
+    def _check_step(self, tau):
+        """Stop at once when the temperature cannot advance: a zero step below temperature 1 (the
+        device also sets SMC_FLAG_STALL) would leave every later stage where this one is."""
+        if tau < 1.0 and float(self.h.item()) == 0.0:
+            raise RuntimeError("temperature bisection stalled at stage %d (tau = %.17g)" % (self.stage, tau))
 
     def run(self, max_stages=500):
         self.initialise()
@@ -132,6 +139,7 @@ class SMCGMSampler(SMCSampler):
         smc.smc_gather(N, p.K, self.idx, self.xi, self.phi, self.xi2, self.phi2)
         self.xi, self.xi2 = self.xi2, self.xi
         self.tau.copy_(self.tau_new)
+        self._check_step(float(self.tau.item()))
         gm = fit_mixture(p, N, self.xi, self.M, self.seed, base, self.fit_iters)
         smc.smc_gm_draw(p, N, gm, self.seed, base, None, self.prec, self.xi2, self.phi)
         self.xi, self.xi2 = self.xi2, self.xi
@@ -241,6 +249,9 @@ class MixedSampler:
             taus = self.tau.cpu().numpy()
             hs = self.h.cpu().numpy()
             lzs = self.log_z.cpu().numpy()
+            for g in self.running:
+                if taus[g] < 1.0 and hs[g] == 0.0:
+                    raise RuntimeError("temperature bisection of sampler %d stalled at stage %d" % (g, self.stage))
             for g in list(self.running):
                 r = self.rows(g)
                 rate = float(acc[r].sum()) / (self.counts[g] * max(1, self.n_moves))

@@ -361,6 +361,10 @@ def test_temper_edge_cases():
     flags.zero_()
     smc.smc_temper(64, t(np.full(64, np.inf)), t([0.0]), 0.5, h, tau_new, W, lz, flags)
     assert flags.item() & smc.FLAG_NONFINITE
+    flags.zero_()                                     # already at temperature 1: a zero step, no stall
+    smc.smc_temper(64, t(inputs.potentials(64, 80)), t([1.0]), 0.5, h, tau_new, W, lz, flags)
+    assert h.item() == 0.0 and tau_new.item() == 1.0 and flags.item() == 0
+    assert np.allclose(W.cpu().numpy(), 1.0 / 64, rtol=1e-14)
 
 
 @pytest.mark.parametrize("N", [1, 7, 1000, 4096, 16384, 20000, 1 << 20])
@@ -372,6 +376,51 @@ def test_resample_bit_exact(N, kind):
     u = inputs.u53(N)
     idx = torch.empty(N, dtype=torch.int32, device=DEV)
     smc.smc_resample(N, t(W), u, idx)
+    assert idx.cpu().numpy().tolist() == systematic(W, u)
+
+
+@pytest.mark.parametrize("case", ["above_one", "negative", "nan", "inf", "sum_too_large", "exp_weights", "zero"])
+def test_resample_rejects_weights_it_cannot_quantise(case):
+    """Weights must be normalised (each in [0, 1], total at most 1 + 2N 2^-53): anything else sets
+    SMC_FLAG_BADWEIGHTS and gives the identity, instead of a wrapped integer CDF."""
+    from paper_2503_16028_amd import smc
+    banner("resample rejects", case)
+    N = 4096
+    W = inputs.weights(N, 77, "dirichlet")
+    if case == "above_one":
+        W[100] = 1.5
+    elif case == "negative":
+        W[5] = -W[5]
+    elif case == "nan":
+        W[4095] = np.nan
+    elif case == "inf":
+        W[0] = np.inf
+    elif case == "sum_too_large":
+        W = W * (1.0 + 1e-9)
+    elif case == "exp_weights":                       # exp(-h (Phi - Phi_min)) in (0, 1], not normalised
+        W = np.exp(-0.01 * inputs.potentials(N, 78))
+        W /= W.max()
+    else:
+        W[:] = 0.0
+    idx = torch.empty(N, dtype=torch.int32, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    smc.smc_resample(N, t(W), inputs.u53(N), idx, flags)
+    assert flags.item() == smc.FLAG_BADWEIGHTS
+    assert np.array_equal(idx.cpu().numpy(), np.arange(N))
+
+
+def test_resample_accepts_normalisation_rounding():
+    """A total just inside the bound 1 + 2N 2^-53 is still resampled, bit-exact with the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("resample rounding slack")
+    N = 1000
+    W = inputs.weights(N, 79, "dirichlet")
+    W[np.argmax(W)] += N * 2.0 ** -53
+    u = inputs.u53(N + 1)
+    idx = torch.empty(N, dtype=torch.int32, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    smc.smc_resample(N, t(W), u, idx, flags)
+    assert flags.item() == 0
     assert idx.cpu().numpy().tolist() == systematic(W, u)
 
 
