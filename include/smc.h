@@ -299,6 +299,22 @@ int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M, int32_t it
                uint64_t seed, uint64_t ctr, double* logw, double* mean, double* scale, int32_t* centers,
                smc_stream stream);
 
+/* The fit of smc_gm_fit without a problem handle and without allocating device memory, for
+ * callers that cannot allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Its workspace is a fixed array in the library's device image (about 8.8 MB,
+ * held by each device the library runs on until the process ends), so
+ *   1 <= N <= smc_gm_fit_noalloc_max() (32768); larger N returns SMC_E_INVAL.
+ *   active [kr] device int32: the coordinates of xi[N][K] to fit (the problem's active modes in
+ *          smc_gm_fit), each in 0..K-1; 1 <= kr <= min(64, K), K <= 1024.
+ * Other arguments, outputs and results as smc_gm_fit (the same kernels: bit-identical results for
+ * the same inputs).  Every call on a device shares that device's array, which keeps the last
+ * call's contents (nothing in it must start at zero): calls that overlap on one device, on any
+ * streams, race and give wrong results. */
+int smc_gm_fit_noalloc(int64_t N, int32_t K, int32_t kr, const int32_t* active, const double* xi, int32_t M,
+                       int32_t iters, double var_floor, uint64_t seed, uint64_t ctr, double* logw, double* mean,
+                       double* scale, int32_t* centers, smc_stream stream);
+int64_t smc_gm_fit_noalloc_max(void);
+
 /* Re-weighting and next temperature (Alg. 1; App. C): with tau = *tau_in (device scalar),
  * choose h in (0, 1 - tau] with ESS(h) = ess_frac * N, where ESS = 1 / sum W^2 and
  * W_n ∝ exp(-h Phi_n): the largest h (to a relative 2^-52, or (1 - tau) 2^-64) whose ESS still

@@ -733,6 +733,26 @@ extern "C" int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M,
     return SMC_OK;
 }
 
+extern "C" int64_t smc_gm_fit_noalloc_max(void) { return STATIC_FIT_N; }
+
+extern "C" int smc_gm_fit_noalloc(int64_t N, int32_t K, int32_t kr, const int32_t* active, const double* xi, int32_t M,
+                                  int32_t iters, double var_floor, uint64_t seed, uint64_t ctr, double* logw,
+                                  double* mean, double* scale, int32_t* centers, smc_stream stream) {
+    if (N < 1 || N > STATIC_FIT_N)
+        return fail(SMC_E_INVAL, "N = %lld outside 1..%lld (the static workspace's size)", (long long)N,
+                    (long long)STATIC_FIT_N);
+    if (K < 1 || K > 1024) return fail(SMC_E_INVAL, "K must be 1..1024");
+    if (kr < 1 || kr > MAX_KR || kr > K) return fail(SMC_E_INVAL, "kr must be 1..min(64, K)");
+    if (M < 1 || M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (iters < 0 || iters > 100000) return fail(SMC_E_INVAL, "iters must be 0..100000");
+    if (!(var_floor > 0.0) || !std::isfinite(var_floor)) return fail(SMC_E_INVAL, "var_floor must be positive");
+    if (!active || !xi || !logw || !mean || !scale)
+        return fail(SMC_E_INVAL, "active, xi, logw, mean and scale must not be NULL");
+    HIPCHK(launch_gm_fit_static(N, K, kr, active, xi, M, iters, var_floor, seed, ctr, centers, logw, mean, scale,
+                                (hipStream_t)stream));
+    return SMC_OK;
+}
+
 extern "C" int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, double tau,
                               int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level, int32_t prec,
                               double* xi, double* phi, int32_t* n_acc, smc_stream stream) {

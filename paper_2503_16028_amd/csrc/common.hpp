@@ -265,6 +265,13 @@ struct FitWorkspace {
     double* part;
 };
 int64_t em_blocks(int64_t N);
+// Mixture fit on the library's static scratch array (no allocation), for up to STATIC_FIT_N
+// particles; launch_gm_fit_static returns hipErrorInvalidValue beyond that.
+constexpr int64_t STATIC_FIT_N = 32768;
+size_t static_fit_bytes();
+hipError_t launch_gm_fit_static(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                                double var_floor, uint64_t seed, uint64_t ctr, int32_t* centers, double* logw,
+                                double* mean, double* scale, hipStream_t s);
 hipError_t prepare_gmfit_kernels();
 hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
                          double var_floor, uint64_t seed, uint64_t ctr, const FitWorkspace& w, int32_t* centers,

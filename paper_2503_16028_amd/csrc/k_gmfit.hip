@@ -22,6 +22,8 @@
 // kernel adds them in workgroup order, so results never depend on scheduling.  Passing partials
 // between kernels, rather than through a last-workgroup handshake inside one kernel, avoids a
 // device-scope fence per workgroup (an L2 write-back on this part) in every iteration.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace smc {
@@ -456,6 +458,63 @@ hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const 
     }
     gm_output_kernel<<<1, 256, 0, s>>>(M, kr, w.par + (iters & 1) * GM_PAR, logw, mean, scale);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fit without allocation
+// The same fit for callers that cannot allocate device memory (code under graph capture, serving
+// loops): its workspace is one fixed array in the library's device image instead of a problem's
+// allocation, sized for STATIC_FIT_N particles.  Layout in doubles: d2 [STATIC_FIT_N], two parameter
+// blocks [2][GM_PAR], partial sums [em_blocks(STATIC_FIT_N)][MAX_M][1 + 2 MAX_KR], then MAX_M int32
+// seeded rows.  Nothing in it must start at zero: every entry a kernel reads was written earlier in
+// the same call.  Each device holds its own copy, so concurrent calls on one device share it and race.
+namespace {
+constexpr int64_t STATIC_FIT_PART = ((STATIC_FIT_N + EM_P - 1) / EM_P) * MAX_M * (1 + 2 * MAX_KR);
+constexpr int64_t STATIC_FIT_DOUBLES = STATIC_FIT_N + 2 * GM_PAR + STATIC_FIT_PART + MAX_M / 2;
+static_assert(MAX_M % 2 == 0, "seeded rows fill whole doubles");
+static __device__ __align__(256) double scratch[STATIC_FIT_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+double* g_scratch[MAX_DEVICES];   // device address of `scratch` on each device, once resolved
+bool g_prepared[MAX_DEVICES];
+std::mutex g_scratch_mu;
+}  // namespace
+
+size_t static_fit_bytes() { return sizeof(double) * (size_t)STATIC_FIT_DOUBLES; }
+
+// Resolve the device address of the scratch array on the current device (first call per device):
+// the array's name in host code is only a host-side handle, so kernels get this address.
+static hipError_t static_fit_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = (double*)ptr;
+    }
+    if (!g_prepared[dev]) {   // the E-step's LDS above the default limit, set once per device
+        e = prepare_gmfit_kernels();
+        if (e != hipSuccess) return e;
+        g_prepared[dev] = true;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_gm_fit_static(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                                double var_floor, uint64_t seed, uint64_t ctr, int32_t* centers, double* logw,
+                                double* mean, double* scale, hipStream_t s) {
+    if (N <= 0 || N > STATIC_FIT_N) return hipErrorInvalidValue;
+    double* base = nullptr;
+    const hipError_t e = static_fit_scratch(&base);
+    if (e != hipSuccess) return e;
+    FitWorkspace w{base, base + STATIC_FIT_N, base + STATIC_FIT_N + 2 * GM_PAR};
+    int32_t* rows = centers ? centers : (int32_t*)(base + STATIC_FIT_N + 2 * GM_PAR + STATIC_FIT_PART);
+    return launch_gm_fit(N, K, kr, active, xi, M, iters, var_floor, seed, ctr, w, rows, logw, mean, scale, s);
 }
 
 hipError_t prepare_gmfit_kernels() {

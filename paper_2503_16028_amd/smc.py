@@ -69,6 +69,9 @@ _SIGS = {
                                c_vp, c_vp, c_vp, c_vp]),
     "smc_gm_draw": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_u64, c_u64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_gm_fit": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_i32, c_dbl, c_u64, c_u64, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "smc_gm_fit_noalloc": (c_i32, [c_i64, c_i32, c_i32, c_vp, c_vp, c_i32, c_i32, c_dbl, c_u64, c_u64, c_vp, c_vp,
+                                   c_vp, c_vp, c_vp]),
+    "smc_gm_fit_noalloc_max": (c_i64, []),
     "smc_forward_state": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_value_and_grad": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_pcnl_move": (c_i32, [c_vp, c_i64, c_dbl, c_dbl, c_i32, c_u64, c_u64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -290,6 +293,23 @@ def smc_gm_fit(problem, N, xi, M, iters, var_floor, seed, ctr, logw, mean, scale
                             float(var_floor), seed, ctr, _ptr(logw, torch.float64, M, "logw"),
                             _ptr(mean, torch.float64, M * kr, "mean"), _ptr(scale, torch.float64, M * kr, "scale"),
                             _ptr(centers, torch.int32, M, "centers", optional=True), _stream(stream)))
+
+
+def smc_gm_fit_noalloc(N, K, active, xi, M, iters, var_floor, seed, ctr, logw, mean, scale, centers=None,
+                       stream=None):
+    """The same fit without a problem and without allocating: active[kr] (int32, device) lists the
+    coordinates of xi[N][K] to fit; the workspace is the library's static array (N up to
+    smc_gm_fit_noalloc_max())."""
+    kr = int(active.numel())
+    _check(lib().smc_gm_fit_noalloc(N, int(K), kr, _ptr(active, torch.int32, kr, "active"),
+                                    _ptr(xi, torch.float64, N * K, "xi"), int(M), int(iters), float(var_floor), seed,
+                                    ctr, _ptr(logw, torch.float64, M, "logw"), _ptr(mean, torch.float64, M * kr, "mean"),
+                                    _ptr(scale, torch.float64, M * kr, "scale"),
+                                    _ptr(centers, torch.int32, M, "centers", optional=True), _stream(stream)))
+
+
+def smc_gm_fit_noalloc_max():
+    return int(lib().smc_gm_fit_noalloc_max())
 
 
 def smc_forward_state(problem, N, xi, prec, G, w, iters=None, stream=None):

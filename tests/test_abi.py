@@ -24,7 +24,7 @@ def libsmc():
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|uint64_t|const char\*)\s+(smc_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|uint64_t|const char\*)\s+(smc_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_calls():
