@@ -50,21 +50,43 @@ def adapt_beta(beta, rate):
     return beta
 
 
+def _pde_potentials(args):
+    from .forward import phi as phi_pde
+    prob, n, xi = args
+    return np.array([phi_pde(prob, x, n) for x in xi])
+
+
+def _pde_moves(args):
+    prob, n, xi, phi, gm, beta, tau, n_moves, seed, ctr, ids = args
+    return gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, ctr, ids=ids)
+
+
 def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stages=500, xi0=None, ids=None,
-        ctr_off=0):
-    """Returns dict(xi, phi, taus, log_Z, betas, rates).
+        ctr_off=0, pmap=None, chunks=1):
+    """Returns dict(xi, phi, taus, log_Z, betas, rates, n_acc).
 
     A sampler that shares its random streams with others (several samplers in one batch) passes
     its starting cloud xi0, its particles' ids (the words of their streams) and ctr_off, added to
-    the counter of its resampling uniform and its mixture seeding."""
+    the counter of its resampling uniform and its mixture seeding.
+
+    pmap (a map over a list, e.g. a process pool's; PDE potentials only) spreads the potentials
+    of the initial cloud and each stage's moves over `chunks` contiguous blocks of particles.
+    Particles never interact inside a stage's moves and every random number is keyed by the
+    particle's id, so the result is the same as with pmap=None."""
     from .forward import phi as phi_pde
     K = prob.K
     f = phi_fn if phi_fn is not None else (lambda x: phi_pde(prob, x, n))
     active = prob.active() if kr is None else np.arange(kr)
     xi = prior_sample(K, N, seed, 0) if xi0 is None else np.array(xi0, dtype=np.float64)
-    phi = np.array([f(x) for x in xi])
+    par = pmap is not None and phi_fn is None
+    blocks = np.array_split(np.arange(N), max(1, chunks))
+    row_ids = np.arange(N) if ids is None else np.asarray(ids)
+    if par:
+        phi = np.concatenate(list(pmap(_pde_potentials, [(prob, n, xi[b]) for b in blocks])))
+    else:
+        phi = np.array([f(x) for x in xi])
     tau, beta, log_Z = 0.0, float(beta0), 0.0
-    taus, betas, rates = [0.0], [], []
+    taus, betas, rates, accepts = [0.0], [], [], []
     for s in range(1, max_stages + 1):
         h, tau, W, lz, stalled = temper(phi, tau, rho)
         if stalled:
@@ -78,15 +100,23 @@ def run(prob, n, N, M, n_moves, rho, beta0, seed, phi_fn=None, kr=None, max_stag
         else:
             logw, mean, var, _ = gmfit.fit_philox(xi[:, active], M, seed, s * STAGE_STRIDE + ctr_off)
             gm = GM(logw, mean, var, active, K)
-        xi, phi, n_acc = gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
-                                     phi_fn=f, ids=ids)
+        if par:
+            out = list(pmap(_pde_moves, [(prob, n, xi[b], phi[b], gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
+                                          row_ids[b]) for b in blocks]))
+            xi = np.concatenate([o[0] for o in out])
+            phi = np.concatenate([o[1] for o in out])
+            n_acc = np.concatenate([o[2] for o in out])
+        else:
+            xi, phi, n_acc = gmpcn_moves(prob, n, xi, phi, gm, beta, tau, n_moves, seed, s * STAGE_STRIDE,
+                                         phi_fn=f, ids=ids)
         rate = n_acc.sum() / (N * n_moves)
         betas.append(beta)
         rates.append(rate)
+        accepts.append(int(n_acc.sum()))
         beta = adapt_beta(beta, rate)
         if tau >= 1.0:
             break
-    return dict(xi=xi, phi=phi, taus=np.array(taus), log_Z=log_Z, betas=betas, rates=rates)
+    return dict(xi=xi, phi=phi, taus=np.array(taus), log_Z=log_Z, betas=betas, rates=rates, n_acc=accepts)
 
 
 def run_gm(prob, n, N, M, rho, seed, phi_fn=None, kr=None, iters=50, var_floor=1e-3, max_stages=500):

@@ -1,0 +1,133 @@
+"""Whole runs of the GPU sampler against the oracle's runs of the workloads C1, C2 and C3.
+
+The oracle's runs (tests/golden/run_<name>_oracle.json, written by make_run_references.py from
+oracle/ alone) are SMC-pCN-GM, Alg. 1 with the pCN-GM mutation of Alg. 2, in FP64 with a direct
+solve per proposal, from the workload's seed to temperature 1.  Both sides draw every random
+number from the same Philox layout (prior draw, resampling uniform, mixture seeding, component
+choice, normals, acceptance uniform), so:
+
+  * FP64 replay: the GPU's FP64 path with the same seed and particle count makes the same
+    decisions; temperatures agree to 1e-9, step sizes and acceptance counts exactly, log Z to
+    1e-8, the final potentials to 1e-8 relative and the kept particles to 1e-7 relative.  The
+    remaining differences are rounding: an iterative solve to the FP64 residual tolerance
+    against a direct solve, and a mixture fit whose partial sums run in another order.
+  * FP32 CG with FP64 refinement at the benchmark's tolerances (inner 1e-3, outer 1e-10):
+    potentials differ from the oracle's by about 1e-9 relative, so an acceptance decision can
+    only differ where log U lies within about tau Phi 1e-9 of log a; with the workload's seed no
+    decision differs and the run replays the oracle's to the tolerances stated in each test.
+  * The metric configuration (128^2, N = 4096, FP32 + refinement) against the oracle's N = 1024
+    run: posterior moments within Monte Carlo bounds.  A cloud of N particles after resampling
+    and moves is taken to carry the information of N / 4 independent draws (the effective size
+    used throughout these tests); then for every active coordinate
+      |mean_gpu - mean_oracle| <= 4.5 s sqrt(4 / N_gpu + 4 / N_oracle),
+      |std_gpu / std_oracle - 1| <= 4.5 sqrt(2 / N_gpu + 2 / N_oracle),
+    and log Z within LOGZ_TOL (4.5 times the seed-to-seed spread of log Z measured at N = 1024).
+"""
+import json
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import golden
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+LOGZ_TOL = 0.5
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    return json.load(open(golden("problem_%s.json" % name))), json.load(open(golden("run_%s_oracle.json" % name)))
+
+
+def gpu_run(d, ref, N, prec, tol64, tol_inner=1e-3, seed=None):
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCSampler
+    n = ref["grid"]
+    max_iter = 60 * n if prec == smc.SMC_FP64 else 2000
+    p = smc.Problem(d, N, grids=[n], tol64=tol64, tol_inner=tol_inner, max_iter=max_iter, max_sweeps=8)
+    s = SMCSampler(p, N, ref["M"], ref["n_moves"], ess_frac=ref["rho"], beta0=ref["beta0"], prec=prec,
+                   seed=ref["seed"] if seed is None else seed, device=DEV, fit_iters=ref["fit_iters"])
+    out = s.run()
+    torch.cuda.synchronize()
+    assert smc.smc_status_flags(p) == 0
+    xi = out["xi"].cpu().numpy()
+    return dict(taus=[0.0] + [h["tau"] for h in out["history"]], betas=[h["beta"] for h in out["history"]],
+                accepts=[int(round(h["rate"] * N * ref["n_moves"])) for h in out["history"]],
+                log_Z=out["log_Z"], phi=out["phi"].cpu().numpy(), xi=xi)
+
+
+def check_replay(g, ref, tau_rtol, lz_tol, phi_rtol, xi_rtol):
+    assert len(g["taus"]) == len(ref["taus"]), (g["taus"], ref["taus"])
+    rphi, rx = np.asarray(ref["phi"]), np.asarray(ref["xi_keep"])
+    print("[measured] stages %d, tau %.3g, log Z %.3g, phi %.3g, xi %.3g, accepts equal %s" % (
+        len(g["taus"]) - 1, np.abs(np.asarray(g["taus"][1:]) / np.asarray(ref["taus"][1:]) - 1).max(),
+        abs(g["log_Z"] - ref["log_Z"]), np.abs(g["phi"] / rphi - 1).max(),
+        np.abs(g["xi"][ref["keep"]] - rx).max() / np.abs(rx).max(), g["accepts"] == ref["accepts"]), flush=True)
+    assert np.allclose(g["taus"], ref["taus"], rtol=tau_rtol, atol=0)
+    assert g["betas"] == ref["betas"]
+    assert g["accepts"] == ref["accepts"]
+    assert abs(g["log_Z"] - ref["log_Z"]) <= lz_tol
+    rphi = np.asarray(ref["phi"])
+    assert np.abs(g["phi"] / rphi - 1).max() <= phi_rtol
+    rx = np.asarray(ref["xi_keep"])
+    assert np.abs(g["xi"][ref["keep"]] - rx).max() <= xi_rtol * np.abs(rx).max()
+
+
+def test_c1_fp64_replays_the_oracle_run():
+    """1D, 64 intervals, N = 256, plain pCN, 10 moves per stage (the 1D path solves directly)."""
+    from paper_2503_16028_amd import smc
+    banner("c1 replay")
+    d, ref = load("c1")
+    g = gpu_run(d, ref, ref["N"], smc.SMC_FP64, 1e-13)
+    check_replay(g, ref, 1e-9, 1e-8, 1e-8, 1e-7)
+
+
+@pytest.mark.parametrize("name,tol64", [("c2", 1e-13), ("c3", 2e-12)])
+def test_fp64_replays_the_oracle_run(name, tol64):
+    from paper_2503_16028_amd import smc
+    banner("fp64 replay", name)
+    d, ref = load(name)
+    g = gpu_run(d, ref, ref["N"], smc.SMC_FP64, tol64)
+    check_replay(g, ref, 1e-9, 1e-8, 1e-8, 1e-7)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_fp32_refine_at_benchmark_tolerances_replays_the_oracle_run(name):
+    from paper_2503_16028_amd import smc
+    banner("fp32+refine replay", name)
+    d, ref = load(name)
+    g = gpu_run(d, ref, ref["N"], smc.SMC_FP32_REFINE, 1e-10, 1e-3)
+    check_replay(g, ref, 1e-8, 1e-6, 1e-6, 1e-5)
+
+
+def test_c3_metric_configuration_posterior_moments():
+    """128^2, N = 4096, M = 8, FP32 + refinement at the benchmark's tolerances, against the oracle's
+    FP64 run of N = 1024: the moments of the 64 active coordinates and log Z within Monte Carlo
+    bounds (module docstring)."""
+    from paper_2503_16028_amd import smc
+    banner("c3 metric configuration moments")
+    d, ref = load("c3")
+    N = 4096
+    g = gpu_run(d, ref, N, smc.SMC_FP32_REFINE, 1e-10, 1e-3, seed=1)
+    from oracle.problem import Problem as OProblem
+    act = OProblem(d).active()
+    m_o, s_o = np.asarray(ref["mean"])[act], np.asarray(ref["std"])[act]
+    m_g, s_g = g["xi"][:, act].mean(0), g["xi"][:, act].std(0)
+    No = ref["N"]
+    z_mean = np.abs(m_g - m_o) / (s_o * math.sqrt(4.0 / N + 4.0 / No))
+    z_std = np.abs(s_g / s_o - 1) / math.sqrt(2.0 / N + 2.0 / No)
+    print("[measured] max z mean %.2f, max z std %.2f, log Z gpu %.4f oracle %.4f, stages %d / %d" %
+          (z_mean.max(), z_std.max(), g["log_Z"], ref["log_Z"], len(g["taus"]) - 1, len(ref["taus"]) - 1),
+          flush=True)
+    assert g["taus"][-1] == 1.0
+    assert z_mean.max() <= 4.5, z_mean
+    assert z_std.max() <= 4.5, z_std
+    assert abs(g["log_Z"] - ref["log_Z"]) <= LOGZ_TOL
