@@ -47,12 +47,27 @@ def measured_traffic(tile):
         return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(d, sample_per_worker=100):
     """The oracle, as it stands, on a bounded sample of the workload: `workers` processes each
-    run one pCN-GM move for `sample_per_worker` particles (one sparse direct solve each)."""
+    run one pCN-GM move for `sample_per_worker` particles (one sparse direct solve each).  The
+    pool takes every core this process may run on, up to 16: a one-GPU share of the host."""
     import concurrent.futures
     import multiprocessing as mp
-    workers = max(1, min(16, os.cpu_count() or 1))
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    workers = max(1, min(16, usable))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
@@ -62,7 +77,8 @@ def cpu_baseline(d, sample_per_worker=100):
     move_wall = max(r[1] for r in res)
     return dict(value=moves / move_wall, unit="particle-moves/s", cores=workers, kind="oracle",
                 sample="%d particles x 1 pCN-GM move at 128^2 (M=8) over %d processes; %.1f s wall incl. setup"
-                       % (moves, workers, wall))
+                       % (moves, workers, wall),
+                cpu_model=cpu_model(), cpus_usable=usable, cpus_visible=os.cpu_count())
 
 
 def _oracle_chunk(args):
@@ -309,9 +325,14 @@ def main():
         variants.update(smc_gm_variant(dev))
         variants.update(example1_variant(dev))
         variants.update(mixed_variant(dev))
-        t64, prof64, _ = stage_loop(smc.SMC_FP64, 1, 0, 4)
-        variants["fp64_batched_moves_per_s"] = N * 4 / t64
+        # FP64 conjugate gradients with the same preconditioner, on the headline's protocol: the same
+        # seed, stages, warm-up and moves per stage, so the ratio compares precisions alone
+        t64, prof64, _ = stage_loop(smc.SMC_FP64, args.steps, args.warmup, args.moves)
+        variants["fp64_batched_moves_per_s"] = N * args.moves * args.steps / t64
         variants["fp64_batched_solve_ms_per_launch"] = prof64["ms"] / max(1, prof64["launches"])
+        variants["fp64_batched_protocol"] = "%d stages of %d moves after %d warm-up stages" % (
+            args.steps, args.moves, args.warmup)
+        variants["fp32_refine_over_fp64"] = value / variants["fp64_batched_moves_per_s"]
         # the same kernels launched once per particle, FP64
         S, nm, cap = 16, 1, 20.0       # particles, moves each, seconds cap
         xi = torch.empty(S, p.K, dtype=torch.float64, device=dev)
@@ -338,6 +359,14 @@ def main():
         variants["fp64_per_particle_sample"] = "%d particles x %d move, one launch sequence per particle" % (done, nm)
         variants["fp32_refine_batched_moves_per_s"] = value
     traffic = measured_traffic(tile) if fast_poisson else None
+    # HBM roofline of the solve (the forward solves' target is a fraction of the HBM peak): bytes per
+    # launch from the committed FETCH_SIZE/WRITE_SIZE summary of this kernel, over the live launch
+    # time.  The streaming byte model of a Jacobi-PCG solve, U (48 I + 20 S + 12) bytes per solve,
+    # would exceed the HBM peak here: the CG vectors and the transforms stay on chip, and only the
+    # FP64 refinement (field, iterate, scaling) crosses to memory.
+    stream_model = N * (GRID ** 2) * (
+        48.0 * prof32["iters"] / max(1, prof32["solves"]) + 20.0 * prof32["sweeps"] / max(1, prof32["solves"]) + 12.0)
+    hbm_achieved = None if traffic is None else traffic / (kernel_ms * 1e-3)
     out = {
         "metric": "particle GM-pCN moves/sec (solve+Phi) at 128^2, N=4096; FP32+refine vs FP64",
         "value": value,
@@ -358,14 +387,19 @@ def main():
                               "inside FP64 residual refinement to 1e-10") if fast_poisson else
                              "Jacobi-scaled CG in FP32 (no further preconditioner), inside FP64 residual refinement "
                              "to 1e-10"},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / F16_MFMA_PEAK,
+        "roofline": {"bound": "hbm",
+                     "achieved": None if hbm_achieved is None else hbm_achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": None if hbm_achieved is None else hbm_achieved / HBM_PEAK,
                      "traffic": traffic,
-                     "traffic_tb_s": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e12,
-                     "traffic_frac_of_hbm_peak": None if traffic is None else traffic / (kernel_ms * 1e-3) / HBM_PEAK,
-                     "traffic_unit": "bytes per launch",
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a copy)",
                      "kernel": "cg_onchip<float,128,%d,%s>" % (tile, "fast-Poisson" if fast_poisson else "Jacobi"),
                      "kernel_ms_per_launch": kernel_ms,
+                     "streaming_model_bytes_per_launch": stream_model,
+                     "streaming_model_frac": stream_model / (kernel_ms * 1e-3) / HBM_PEAK,
+                     "mfma": {"achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                              "frac": achieved / F16_MFMA_PEAK,
+                              "counts": "8 n^3 FLOP of dense sine-transform products per preconditioner application"},
                      "valu_tflops": valu_flops / (prof32["ms"] * 1e-3) / 1e12,
                      "cg_iters_per_solve": prof32["iters"] / max(1, prof32["solves"]),
                      "precond_apps_per_solve": prof32["precond_apps"] / max(1, prof32["solves"]),

@@ -196,6 +196,13 @@ int smc_gmpcn_move(smc_problem p, int64_t N, const smc_gm* gm, double beta, doub
                    int32_t n_moves, uint64_t seed, uint64_t ctr, const int32_t* level,
                    int32_t prec, double* xi, double* phi, int32_t* n_acc, smc_stream stream);
 
+/* The proposal of smc_gmpcn_move's move 0 by itself (a parity hook): v[N][K] out, drawn as there
+ * from counter ctr, and logr[N] out, the log of rho_0(v) Q(v, xi) / (rho_0(xi) Q(xi, v)) with
+ * rho_0 the prior density and Q the pCN-GM proposal (eqs. (auv of pCN-GMM)-(auv of pCN-GMM4)
+ * without the potential), which the move adds to tau (Phi(xi) - Phi(v)).  v must not alias xi. */
+int smc_gmpcn_propose(smc_problem p, int64_t N, const smc_gm* gm, double beta, uint64_t seed, uint64_t ctr,
+                      const double* xi, double* v, double* logr, smc_stream stream);
+
 /* Parameters of a move stage for several independent samplers at once, all in device memory
  * so that a captured stage can be replayed after they change.  Group g (the particles with
  * level[n] == g, or every particle without a level map) has its own mixture, beta and tau:

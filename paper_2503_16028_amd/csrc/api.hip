@@ -733,6 +733,33 @@ extern "C" int smc_gm_fit(smc_problem p, int64_t N, const double* xi, int32_t M,
     return SMC_OK;
 }
 
+extern "C" int smc_gmpcn_propose(smc_problem p, int64_t N, const smc_gm* gm, double beta, uint64_t seed, uint64_t ctr,
+                                 const double* xi, double* v, double* logr, smc_stream stream) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    const Problem& P = p->P;
+    if (int r = check_gm(P, gm)) return r;
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SMC_E_INVAL, "beta must be in (0, 1]");
+    if (int r = check_n(P, N)) return r;
+    if (N > 0 && (!xi || !v || !logr)) return fail(SMC_E_INVAL, "xi, v and logr must not be NULL");
+    if (xi == v) return fail(SMC_E_INVAL, "v must not alias xi");
+    if (N > 0xFFFFFFFFll) return fail(SMC_E_INVAL, "N exceeds the 32-bit particle counter");
+    if (N == 0) return SMC_OK;
+    MoveParams q;
+    q.beta = beta;
+    q.tau = 0.0;
+    q.seed = seed;
+    q.ctr = ctr;
+    q.M = gm->M;
+    q.kr = gm->kr;
+    q.logw = gm->logw;
+    q.mean = gm->mean;
+    q.scale = gm->scale;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_mixtab(q, P.ws_mixtab, s));
+    HIPCHK(launch_propose(N, P.K, P.active, P.slot, q, P.ws_mixtab, xi, v, logr, P.flags, s));
+    return SMC_OK;
+}
+
 extern "C" int64_t smc_gm_fit_noalloc_max(void) { return STATIC_FIT_N; }
 
 extern "C" int smc_gm_fit_noalloc(int64_t N, int32_t K, int32_t kr, const int32_t* active, const double* xi, int32_t M,

@@ -67,6 +67,7 @@ _SIGS = {
     "smc_potential": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "smc_gmpcn_move": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_dbl, c_dbl, c_i32, c_u64, c_u64, c_vp, c_i32,
                                c_vp, c_vp, c_vp, c_vp]),
+    "smc_gmpcn_propose": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_dbl, c_u64, c_u64, c_vp, c_vp, c_vp, c_vp]),
     "smc_gm_draw": (c_i32, [c_vp, c_i64, ctypes.POINTER(GMDesc), c_u64, c_u64, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_gm_fit": (c_i32, [c_vp, c_i64, c_vp, c_i32, c_i32, c_dbl, c_u64, c_u64, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "smc_gm_fit_noalloc": (c_i32, [c_i64, c_i32, c_i32, c_vp, c_vp, c_i32, c_i32, c_dbl, c_u64, c_u64, c_vp, c_vp,
@@ -275,6 +276,14 @@ def smc_gmpcn_move(problem, N, gm, beta, tau, n_moves, seed, ctr, level, prec, x
                                 ctr, _ptr(level, torch.int32, N, "level", optional=True), prec,
                                 _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(phi, torch.float64, N, "phi"),
                                 _ptr(n_acc, torch.int32, N, "n_acc"), _stream(stream)))
+
+
+def smc_gmpcn_propose(problem, N, gm, beta, seed, ctr, xi, v, logr, stream=None):
+    """The pCN-GM proposal v[N][K] of move counter ctr and its log ratio logr[N] (no potential)."""
+    d = gm_desc(*gm)
+    _check(lib().smc_gmpcn_propose(problem.handle, N, ctypes.byref(d), float(beta), seed, ctr,
+                                   _ptr(xi, torch.float64, N * problem.K, "xi"), _ptr(v, torch.float64, N * problem.K, "v"),
+                                   _ptr(logr, torch.float64, N, "logr"), _stream(stream)))
 
 
 def smc_gm_draw(problem, N, gm, seed, ctr, level, prec, xi, phi, iters=None, stream=None):

@@ -1,10 +1,10 @@
 """Adjoint gradient, forward-state checkpointing, the potential's autograd function and the
 pCN-Langevin move against the oracle (GPU).
 
-Tolerances: gradients on the FP64 path within 1e-8 of the largest oracle component, on the
-FP32+refinement path within 1e-5 (both solves are refined to the FP64 tolerance, and the
-adjoint's right-hand side G - y loses the leading digits G and y share); potentials 1e-10
-relative (FP64); accept counts bit-exact.
+Tolerances: gradients on the FP64 path within 1e-10 of the largest oracle component, on the
+FP32+refinement path within 1e-8 (both solves are refined to the FP64 tolerance; the components
+span many orders of magnitude, sqrt(lambda_k) falling like 1/k^2, so the error is measured against
+the largest); potentials 1e-10 relative (FP64); accept counts bit-exact.
 """
 import json
 import sys
@@ -77,7 +77,7 @@ def test_value_and_grad_fp64(name, grid, N):
     for k in range(N):
         rphi, rg = value_and_grad(op, xi[k], grid)
         assert abs(phi[k] / rphi - 1) <= 1e-10
-        assert np.abs(g[k] - rg).max() <= 1e-8 * np.abs(rg).max(), (k, np.abs(g[k] - rg).max(), np.abs(rg).max())
+        assert np.abs(g[k] - rg).max() <= 1e-10 * np.abs(rg).max(), (k, np.abs(g[k] - rg).max(), np.abs(rg).max())
     assert smc.smc_status_flags(p) == 0
 
 
@@ -93,16 +93,20 @@ def test_value_and_grad_fp32_refine(name, grid, N):
     for k in range(N):
         rphi, rg = value_and_grad(op, xi[k], grid)
         assert abs(phi[k] / rphi - 1) <= 1e-4
-        assert np.abs(g[k] - rg).max() <= 1e-5 * np.abs(rg).max()
+        assert np.abs(g[k] - rg).max() <= 1e-8 * np.abs(rg).max()
 
 
-def test_gradient_central_differences():
+@pytest.mark.parametrize("name,grid", [("t2", 32), ("c4", 128)])
+def test_gradient_central_differences(name, grid):
     """g . d against (Phi(xi + h d) - Phi(xi - h d)) / 2h, h = 1e-6, 16 seeded unit directions,
-    with Phi from the library's FP64 forward solves."""
+    with Phi from the library's FP64 forward solves; at 128^2 on the pCN-Langevin workload's
+    problem.  The difference quotient carries the potentials' own error, at most 2e-12 relative
+    on these grids (3e-13 measured at 128^2), amplified by Phi / h: the bound allows that on top
+    of 1e-6 of the largest directional derivative."""
     from paper_2503_16028_amd import smc
-    banner("central differences 16 directions")
-    d, op = load("t2")
-    grid, D = 32, 16
+    banner("central differences 16 directions", name, grid)
+    d, op = load(name)
+    D = 16
     p = fp64_problem(d, 2 * D + 1, grid)
     x0 = inputs.particles(1, op.K, 23)[0]
     dirs = inputs.particles(D, op.K, 24)
@@ -117,8 +121,27 @@ def test_gradient_central_differences():
     ph = phi.cpu().numpy()
     fd = (ph[1:D + 1] - ph[D + 1:]) / (2 * h)
     an = dirs @ g[0]
-    assert np.abs(fd - an).max() <= 1e-6 * np.abs(g[0]).sum() / np.sqrt(op.K), (fd, an)
-    assert np.abs(fd - an).max() <= 1e-5 * np.abs(an).max()
+    err = np.abs(fd - an).max()
+    print("[measured] central differences %s %d: max |fd - g.d| %.3g, max |g.d| %.3g, Phi %.4g" %
+          (name, grid, err, np.abs(an).max(), ph[0]), flush=True)
+    assert err <= 1e-6 * np.abs(an).max() + 2 * 2e-12 * ph[0] / (2 * h), (fd, an)
+
+
+def test_value_and_grad_c4_full_size_sampled():
+    """The pCN-Langevin workload's launch (128^2, N = 2048, FP32 + refinement at the benchmark's
+    tolerances): potentials and gradients of 8 particles spread over the batch against the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("value_and_grad c4 full size")
+    d, op = load("c4")
+    N = 2048
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    xi = inputs.particles(N, op.K, 32)
+    phi, g, it = gpu_value_and_grad(p, t(xi), smc.SMC_FP32_REFINE)
+    assert (it > 0).all() and smc.smc_status_flags(p) == 0
+    for k in np.linspace(0, N - 1, 8).astype(int):
+        rphi, rg = value_and_grad(op, xi[k], 128)
+        assert abs(phi[k] / rphi - 1) <= 1e-4
+        assert np.abs(g[k] - rg).max() <= 1e-8 * np.abs(rg).max()
 
 
 def test_gradient_taylor_remainder():

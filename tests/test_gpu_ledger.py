@@ -1,0 +1,171 @@
+"""Precision ledger at the metric configuration (128^2, the mirrored-observation problem, 1024
+modes, 8-component mixture): the largest error against the FP64 oracle of every result the move
+stage produces, on both precisions, each printed as a "[ledger]" line and held to its contract.
+
+  G      forward map at the observation nodes, element-wise relative (every observed state value
+         is positive: the discrete operator is an M-matrix and f = 1)
+  Phi    potential, relative
+  log R  the proposal's log ratio (smc_gmpcn_propose against the oracle's plain density ratio
+         with tau = 0), absolute over max(1, |log R|)
+  h, W, log Z  tempering of the potentials of the same cloud (W element-wise over the largest W)
+  grad   dPhi/dxi, largest component error over the largest component
+Sizes: 64 sampled particles of a 4096-particle batch (the benchmark's launch) for G and Phi,
+4096 proposals for log R, 4096 potentials for tempering, 8 particles for the gradient.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from conftest import golden
+from oracle.adjoint import value_and_grad
+from oracle.forward import observe, potential, solve
+from oracle.moves import GM, log_ratio_gmpcn, propose_gmpcn
+from oracle import philox
+from oracle.problem import Problem as OProblem, synthesize
+from oracle.temper import temper
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+N_BATCH = 4096
+PICK = np.linspace(0, N_BATCH - 1, 64).astype(int)
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def ledger(name, prec, value):
+    print("[ledger] %s" % json.dumps(dict(quantity=name, precision=prec, max_error=float(value))), flush=True)
+
+
+def t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    d = json.load(open(golden("problem_c3.json")))
+    return d, OProblem(d)
+
+
+@pytest.fixture(scope="module")
+def cloud(c3):
+    """Prior draws of the library's generator (the first stage's cloud) and the oracle's G of the
+    sampled rows."""
+    d, op = c3
+    xi = philox.normals(2503, 0, np.arange(N_BATCH), op.K)
+    ref_G = np.array([observe(op, solve(op, synthesize(op, x, 128), 128), 128) for x in xi[PICK]])
+    return xi, ref_G
+
+
+PRECS = {"fp64": dict(prec=0, tol64=2e-12, tol_inner=1e-3), "fp32_refine": dict(prec=1, tol64=1e-10, tol_inner=1e-3)}
+G_TOL = {"fp64": 1e-10, "fp32_refine": 1e-7}
+PHI_TOL = {"fp64": 1e-10, "fp32_refine": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_forward_and_potential(c3, cloud, prec):
+    from paper_2503_16028_amd import smc
+    banner("ledger G, Phi", prec)
+    d, op = c3
+    xi, ref_G = cloud
+    cfg = PRECS[prec]
+    p = smc.Problem(d, N_BATCH, tol64=cfg["tol64"], tol_inner=cfg["tol_inner"], max_iter=8000)
+    G = torch.empty(N_BATCH, op.n_obs, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N_BATCH, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N_BATCH, t(xi), None, cfg["prec"], G)
+    smc.smc_potential(p, N_BATCH, G, phi)
+    g = G.cpu().numpy()[PICK]
+    ph = phi.cpu().numpy()[PICK]
+    assert (ref_G > 0).all()
+    eG = np.abs(g / ref_G - 1).max()
+    ePhi = np.abs(ph / potential(ref_G, op.y, op.sigma) - 1).max()
+    ledger("G", prec, eG)
+    ledger("Phi", prec, ePhi)
+    assert eG <= G_TOL[prec]
+    assert ePhi <= PHI_TOL[prec]
+
+
+def test_log_ratio(c3):
+    from paper_2503_16028_amd import smc
+    banner("ledger log R")
+    d, op = c3
+    N, M, beta = N_BATCH, 8, 0.3
+    p = smc.Problem(d, N)
+    xi = inputs.particles(N, op.K, 61, 0.7)
+    logw, mean, scale = inputs.mixture(M, op.kr, 62, spread=0.5)
+    gm = GM(logw, mean, scale, op.active(), op.K)
+    v = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    lr = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_gmpcn_propose(p, N, (t(logw), t(mean), t(scale)), beta, 5, 77, t(xi), v, lr)
+    torch.cuda.synchronize()
+    v, lr = v.cpu().numpy(), lr.cpu().numpy()
+    ids = np.arange(N)
+    z = philox.normals(5, 77, ids, op.K)
+    uc, _ = philox.move_uniforms(5, 77, ids)
+    rows = np.arange(0, N, 16)
+    err_v, err_r = 0.0, 0.0
+    for k in rows:
+        rv, _ = propose_gmpcn(gm, beta, xi[k], z[k], uc[k])
+        err_v = max(err_v, np.abs(v[k] - rv).max() / np.abs(rv).max())
+        rr = log_ratio_gmpcn(gm, beta, 0.0, xi[k], 0.0, rv, 0.0)
+        err_r = max(err_r, abs(lr[k] - rr) / max(1.0, abs(rr)))
+    ledger("proposal v", "fp64", err_v)
+    ledger("log R", "fp64", err_r)
+    assert err_v <= 1e-13
+    assert err_r <= 1e-10
+
+
+def test_tempering(c3, cloud):
+    from paper_2503_16028_amd import smc
+    banner("ledger h, W, log Z")
+    d, op = c3
+    xi, _ = cloud
+    p = smc.Problem(d, N_BATCH, tol64=1e-10, tol_inner=1e-3)
+    G = torch.empty(N_BATCH, op.n_obs, dtype=torch.float64, device=DEV)
+    phi = torch.empty(N_BATCH, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N_BATCH, t(xi), None, smc.SMC_FP32_REFINE, G)
+    smc.smc_potential(p, N_BATCH, G, phi)
+    worst = dict(h=0.0, W=0.0, logZ=0.0)
+    for tau in (0.0, 0.37):
+        h, tau_new, lz = (torch.empty(1, dtype=torch.float64, device=DEV) for _ in range(3))
+        W = torch.empty(N_BATCH, dtype=torch.float64, device=DEV)
+        smc.smc_temper(N_BATCH, phi, t([tau]), 0.5, h, tau_new, W, lz)
+        torch.cuda.synchronize()
+        rh, rtau, rW, rlz, stalled = temper(phi.cpu().numpy(), tau, 0.5)   # the same potentials
+        worst["h"] = max(worst["h"], abs(h.item() / rh - 1))
+        worst["W"] = max(worst["W"], np.abs(W.cpu().numpy() - rW).max() / rW.max())
+        worst["logZ"] = max(worst["logZ"], abs(lz.item() / rlz - 1))
+    for k, v in worst.items():
+        ledger(k, "fp64", v)
+        assert v <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_gradient(c3, prec):
+    from paper_2503_16028_amd import smc
+    banner("ledger gradient", prec)
+    d, op = c3
+    N = 8
+    cfg = PRECS[prec]
+    p = smc.Problem(d, N, tol64=cfg["tol64"], tol_inner=cfg["tol_inner"], max_iter=8000)
+    xi = philox.normals(2503, 0, np.arange(N), op.K)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    g = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    smc.smc_value_and_grad(p, N, t(xi), cfg["prec"], None, phi, g)
+    torch.cuda.synchronize()
+    g, phi = g.cpu().numpy(), phi.cpu().numpy()
+    eg, ep = 0.0, 0.0
+    for k in range(N):
+        rphi, rg = value_and_grad(op, xi[k], 128)
+        eg = max(eg, np.abs(g[k] - rg).max() / np.abs(rg).max())
+        ep = max(ep, abs(phi[k] / rphi - 1))
+    ledger("grad", prec, eg)
+    ledger("Phi (adjoint call)", prec, ep)
+    assert ep <= PHI_TOL[prec]
+    assert eg <= (1e-8 if prec == "fp64" else 1e-5)

@@ -1,7 +1,9 @@
 """Parity of every C ABI call with the oracle on identical seeded inputs (GPU).
 
-Tolerances: FP64 path 1e-10 relative; FP32+refinement 1e-4 relative on potentials;
-integer work (resampling indices, accept counts) bit-exact.
+Tolerances, element-wise: FP64 path 1e-10 relative (the observed states are positive, so every
+element has a relative error; particle coefficients, which cross zero, 1e-10 relative above 1 in
+magnitude and absolute below); FP32+refinement: observations 1e-9 relative, potentials 1e-4
+relative; integer work (resampling indices, accept counts) bit-exact.
 """
 import json
 import math
@@ -107,7 +109,10 @@ def test_forward_fp64(name, grid, N):
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
     assert (it.cpu().numpy() > 0).all()
-    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert (ref > 0).all()                              # observed states are positive (M-matrix, f = 1)
+    err = np.abs(G.cpu().numpy() / ref - 1).max()       # element-wise relative
+    print("[measured] forward fp64 %s %d: %.3g" % (name, grid, err), flush=True)
+    assert err <= 1e-10
     assert smc.smc_status_flags(p) == 0
 
 
@@ -125,7 +130,9 @@ def test_forward_fp32_refine(name, grid, N):
     smc.smc_potential(p, N, G, phi)
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
-    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    err = np.abs(G.cpu().numpy() / ref - 1).max()       # element-wise relative
+    print("[measured] forward fp32+refine %s %d: %.3g" % (name, grid, err), flush=True)
+    assert err <= 1e-9
     if grid in (32, 64, 128, 256):                      # fast-Poisson preconditioner: grid-independent
         assert (it.cpu().numpy() < 60).all(), it
     ref_phi = potential(ref, op.y, op.sigma)
@@ -179,7 +186,7 @@ def test_forward_fp32_jacobi_only(name, grid, N):
     smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP32_REFINE, G, it)
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
-    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    assert np.abs(G.cpu().numpy() / ref - 1).max() <= 1e-9
     assert (it.cpu().numpy() > 3 * grid).all()          # Jacobi needs O(n) iterations per decade
 
 
@@ -197,7 +204,7 @@ def test_forward_fp64_jacobi_only(name, grid, N):
     smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP64, G, it)
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
-    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(G.cpu().numpy() / ref - 1).max() <= 1e-10
     assert (it.cpu().numpy() > 3 * grid).all()          # Jacobi needs O(n) iterations per decade
     assert smc.smc_status_flags(p) == 0
 
@@ -214,7 +221,7 @@ def test_forward_1d(name, grid):
     smc.smc_forward_batch(p, N, t(xi), None, smc.SMC_FP64, G)
     torch.cuda.synchronize()
     ref = oracle_G(op, xi, grid)
-    assert np.abs(G.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(G.cpu().numpy() / ref - 1).max() <= 1e-12
 
 
 def test_potential():
@@ -313,8 +320,9 @@ def test_move_fp64(name, grid, N, M, beta, tau, n_moves):
     xi, phi, acc, rx, rphi, racc = _move_case(name, grid, N, M, beta, tau, n_moves, 0, 11)
     assert np.array_equal(acc, racc)
     assert 0 < acc.sum()
-    assert np.abs(xi - rx).max() <= 1e-10 * np.abs(rx).max()
-    assert np.abs(phi / rphi - 1).max() <= 1e-9
+    # element-wise, relative for |xi| >= 1 and absolute below (coefficients cross zero)
+    assert (np.abs(xi - rx) <= 1e-10 * np.maximum(1.0, np.abs(rx))).all()
+    assert np.abs(phi / rphi - 1).max() <= 1e-10
 
 
 def test_move_fp32_refine():
@@ -342,7 +350,10 @@ def test_temper(N, tau):
     assert h.item() == pytest.approx(rh, rel=1e-10, abs=1e-300)
     assert tau_new.item() == pytest.approx(rtau, rel=1e-12)
     assert lz.item() == pytest.approx(rlz, rel=1e-10, abs=1e-10)
-    assert np.abs(Wt.cpu().numpy() - rW).max() <= 1e-10 * rW.max()
+    Wg = Wt.cpu().numpy()
+    pos = rW > 0
+    assert np.array_equal(Wg[~pos], rW[~pos])           # non-finite potentials weigh exactly 0
+    assert np.abs(Wg[pos] / rW[pos] - 1).max() <= 1e-10    # element-wise relative
     assert flags.item() == 0
 
 
@@ -443,13 +454,14 @@ def test_gather():
 # ------------------------------------------------------------------ full size, sampled
 
 def test_full_size_metric_configuration_sampled():
-    """128^2, N = 4096, FP32 + refinement, in the launch configuration the benchmark times:
-    one move for every particle; sampled particles replayed by the oracle."""
+    """128^2, N = 4096, FP32 + refinement at the benchmark's tolerances (inner 1e-3, outer 1e-10),
+    in the launch configuration the benchmark times: one move for every particle; 64 particles
+    spread over the batch replayed by the oracle."""
     from paper_2503_16028_amd import smc
     banner("full size 128^2 N=4096")
     d, op = load("c3")
     N = 4096
-    p = gpu_problem(d, N, tol64=1e-10, tol_inner=1e-5)
+    p = gpu_problem(d, N, tol64=1e-10, tol_inner=1e-3)
     xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
     smc.smc_prior_sample(p, N, 2503, 0, xi)
     G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
@@ -460,7 +472,7 @@ def test_full_size_metric_configuration_sampled():
     xi_h = xi.cpu().numpy()
     phi_h = phi.cpu().numpy()
     assert (it.cpu().numpy() > 0).all() and np.isfinite(phi_h).all()
-    pick = [0, 1, 777, 2048, 4095]
+    pick = sorted(set(np.linspace(0, N - 1, 62).astype(int).tolist()) | {1, 777})
     ref = potential(oracle_G(op, xi_h[pick], 128), op.y, op.sigma)
     assert np.abs(phi_h[pick] / ref - 1).max() <= 1e-4
     logw, mean, scale = inputs.mixture(8, op.kr, 43, spread=0.5)
