@@ -229,8 +229,68 @@ def mixed_variant(dev, counts=(4096, 3072, 1024), n_moves=20, stages=2):
             "mixed_counts": list(counts)}
 
 
+SOLVE_ONLY = {
+    # name: (problem, grids, particles per grid, precision)
+    "c3_fp32": ("c3", [128], [4096], 1),
+    "c3_fp64": ("c3", [128], [4096], 0),
+    "c5_256_fp32": ("c5", [256], [1024], 1),
+    "c5_mixed_fp32": ("c5", [64, 128, 256], [4096, 3072, 1024], 1),
+    "c4_adjoint_fp32": ("c4", [128], [2048], 1),
+}
+
+
+def solve_only(name, reps, copy_probe):
+    """Forward solves (synthesis and solve) of one workload, `reps` timed launches after one warm-up:
+    the command the solvers' counter profiles are taken with.  c5_mixed_fp32 solves the three grids
+    in one persistent launch (a level map); c4_adjoint_fp32 also solves the adjoint (the gradient)."""
+    import torch
+    from paper_2503_16028_amd import smc
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob, grids, counts, prec = SOLVE_ONLY[name]
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_%s.json" % prob)))
+    N = sum(counts)
+    p = smc.Problem(d, N, grids=grids, tol64=1e-10, tol_inner=1e-3)
+    xi = torch.empty(N, p.K, dtype=torch.float64, device=dev)
+    smc.smc_prior_sample(p, N, 2503, 0, xi)
+    level = None
+    if len(grids) > 1:
+        level = torch.cat([torch.full((c,), l, dtype=torch.int32) for l, c in enumerate(counts)]).to(dev)
+    G = torch.empty(N, p.n_obs, dtype=torch.float64, device=dev)
+    grad = torch.empty(N, p.K, dtype=torch.float64, device=dev)
+    phi = torch.empty(N, dtype=torch.float64, device=dev)
+
+    def launch():
+        if name.startswith("c4_adjoint"):
+            smc.smc_value_and_grad(p, N, xi, prec, None, phi, grad)
+        else:
+            smc.smc_forward_batch(p, N, xi, level, prec, G)
+
+    if copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
+    launch()
+    torch.cuda.synchronize()
+    smc.smc_profile(p, 1)
+    for _ in range(reps):
+        launch()
+    pr = smc.smc_profile_read(p)
+    smc.smc_profile(p, 0)
+    assert smc.smc_status_flags(p) == 0
+    print(json.dumps({"solve_only": name, "particles": counts, "grids": grids, "precision": "fp64" if prec == 0 else
+                      "fp32+refine", "launches": pr["launches"], "ms_per_launch": pr["ms"] / max(1, pr["launches"]),
+                      "cg_iters_per_solve": pr["iters"] / max(1, pr["solves"]),
+                      "sweeps_per_solve": pr["sweeps"] / max(1, pr["solves"]),
+                      "precond_apps_per_solve": pr["precond_apps"] / max(1, pr["solves"])}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--solve-only", choices=sorted(SOLVE_ONLY),
+                    help="time only the forward solves of one workload (the solvers' profiling command)")
+    ap.add_argument("--reps", type=int, default=5, help="timed launches of --solve-only")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -248,6 +308,9 @@ def main():
         print("bench.py runs the move stage on one GPU only (--gpus %d requested); the multi-GPU sharding "
               "is a design, not part of this build" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.solve_only:
+        solve_only(args.solve_only, args.reps, args.copy_probe)
+        return
     d = json.load(open(PROBLEM))
     cpu = None if args.no_cpu else cpu_baseline(d)    # before anything touches the GPU
 

@@ -222,7 +222,7 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     const int64_t nb = P.n_big;
     P.e_stride = P.dim == 2 ? (nb + 1) * (nb + 1) : nb + 1;
     P.x_stride = P.e_stride;
-    P.vec_stride = P.dim == 2 ? 6 * nb * nb : 0;
+    P.vec_stride = P.dim == 2 ? 7 * nb * nb : 0;
     const int64_t Nm = P.n_max;
     ck(hipMalloc((void**)&P.ws_v, sizeof(double) * Nm * K));
     ck(hipMalloc((void**)&P.ws_logr, sizeof(double) * Nm));

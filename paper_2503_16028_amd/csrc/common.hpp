@@ -55,7 +55,7 @@ struct Problem {
     double* ws_gnew = nullptr;   // [n_max][K]              gradient at the proposal (2D)
     double* ws_sd = nullptr;     // [n_max][n_big^2]        D^{-1/2} of the Jacobi scaling (FP32 in the first
                                  //                         half of a row for FP32 on-chip solves)
-    void* ws_vec = nullptr;      // [n_max][6][n_big^2] doubles: vectors of the global-memory solver
+    void* ws_vec = nullptr;      // [n_max][7][n_big^2] doubles: vectors of the global-memory solver
     double* ws_G = nullptr;      // [n_max][n_obs]
     int32_t* ws_iters = nullptr; // [n_max]
     int32_t* ws_list = nullptr;  // [n_max] work list of a level map (particles grouped by grid)

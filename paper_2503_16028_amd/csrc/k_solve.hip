@@ -880,16 +880,26 @@ __device__ __forceinline__ void dstg_apply(const T* __restrict__ r, T* __restric
 }
 
 // The transform as a function of its own, on the module-level buffer the global solvers stage X
-// in: inlined into the CG loop it competes for that loop's registers and both spill.  Returns this
-// thread's share of r.z when `staged` (r already in X as fp16(r 2^-ex)), else 0.
+// in: inlined into the CG loop it competes for that loop's registers and both spill.  `staged`: r
+// is already in X as fp16(r 2^-ex); `want_rz`: returns this thread's share of r.z (else 0).
 static_assert(D256_BYTES <= MIXED_SMEM, "256^2 transform LDS");
 template <int NN, typename T>
 __device__ __noinline__ double dstg_precondition(const T* r, T* z, const _Float16* S, const float* lam, int staged,
-                                                 int ex) {
+                                                 int ex, int want_rz) {
     double rz = 0.0;
     dstg_apply<NN, T>(r, z, reinterpret_cast<_Float16*>(g_mixed_smem), S, lam, ex, staged != 0,
-                      staged ? &rz : nullptr);
+                      want_rz ? &rz : nullptr);
     return rz;
+}
+
+// a * b + c with one rounding, for float and double alike
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>
+__device__ __forceinline__ vec4_t<T> fma4(T a, vec4_t<T> b, vec4_t<T> c) {
+    vec4_t<T> o;
+    o.x = fma_t(a, b.x, c.x); o.y = fma_t(a, b.y, c.y); o.z = fma_t(a, b.z, c.z); o.w = fma_t(a, b.w, c.w);
+    return o;
 }
 
 __global__ __launch_bounds__(1024) void dst256_apply_kernel(const float* __restrict__ rin, float* __restrict__ zout,
@@ -922,7 +932,10 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
     const int nodes = NN * NN;
     const double* e = a.e + row * a.e_stride;
     double* x64 = a.x64 + row * a.x_stride;
-    double* sd = a.sd + row * a.sd_stride;
+    // D^{-1/2} only scales the inner system: FP32 with FP32 inner solves (the update applies the
+    // values the residual was scaled by), inside the particle's own FP64 row
+    using SD = typename std::conditional<std::is_same<T, float>::value, float, double>::type;
+    SD* sd = reinterpret_cast<SD*>(a.sd + row * a.sd_stride);
     T* vb = reinterpret_cast<T*>(reinterpret_cast<double*>(a.vec) + row * a.vec_stride);
     T* tv = vb;
     T* xv = vb + nodes;
@@ -930,17 +943,11 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
     T* pv = vb + 3 * nodes;
     T* qv = vb + 4 * nodes;
     T* yv = vb + 5 * nodes;   // t p (Jacobi path)
-    T* zv = yv;               // preconditioned residual (DST path, which needs no y): six vectors
+    T* zv = yv;               // preconditioned residual (DST path, which needs no y)
+    T* pv2 = vb + 6 * nodes;  // second search-direction buffer (DST path): seven vectors
     const double h = 1.0 / NN, inv_h2 = (double)NN * (double)NN;
     auto interior = [&](int g, int c) { return c < NN - 1 && g < NN - 1; };
     int napp = 0;
-    auto precondition = [&](double rrin) {   // zv = L^{-1} rv, rrin = |rv|^2
-        if constexpr (DST) {
-            // the input at a 2^-3 margin below unit norm, as for the staged applications below
-            (void)dstg_precondition<DN, T>(rv, zv, Stab, lamtab, 0, norm_exponent(rrin) + 3);
-            ++napp;
-        }
-    };
 
     for (int k = tid; k < nodes; k += 1024) {
         const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
@@ -952,7 +959,7 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             sdv = h * rs;
             tt = eP * rs;
         }
-        sd[k] = sdv;
+        sd[k] = (SD)sdv;
         tv[k] = (T)tt;
     }
     __syncthreads();
@@ -997,7 +1004,10 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
         double fnorm = 0.0;
         for (int sweep = 0;; ++sweep) {
             ++sweeps;
-            double acc = 0.0;
+            // residual pass: r = D^{-1/2} (f - A x) in T, with |f - A x|^2 in FP64 and |r|^2 summed on
+            // the way (the fast-Poisson path writes r only: its first transform writes p = z, and the
+            // first update sets x = alpha p)
+            double acc = 0.0, tacc = 0.0;
             for (int k = tid; k < nodes; k += 1024) {
                 const int g = k / NN, c = k % NN, i = c + 1, j = g + 1;
                 T rk = T(0);
@@ -1014,13 +1024,17 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                                 e[(j + 1) * NP1 + i] * (xP - xN) + e[(j - 1) * NP1 + i] * (xP - xS));
                     }
                     acc += res * res;
-                    rk = (T)(sd[k] * res);
+                    rk = (T)((double)sd[k] * res);
+                    tacc += (double)rk * (double)rk;
                 }
                 rv[k] = rk;
-                pv[k] = rk;
-                xv[k] = T(0);
+                if constexpr (!DST) {
+                    pv[k] = rk;
+                    xv[k] = T(0);
+                }
             }
             const double rr64 = block_sum<NW>(acc, red2);
+            double rr = block_sum<NW>(tacc, red1);
             if (sweep == 0) fnorm = sqrt(rr64);
             if (sqrt(rr64) <= a.tol64 * fnorm) {   // at sweep 0 only for a zero right-hand side
                 ok = true;
@@ -1030,72 +1044,95 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             }
             if (!(rr64 < INFINITY) || sweep >= a.max_sweeps || total >= a.max_iter) break;
 
-            double tacc = 0.0;
-            for (int k = tid; k < nodes; k += 1024) tacc += (double)rv[k] * (double)rv[k];
-            double rr = block_sum<NW>(tacc, red1);
-            double rz = rr;
-            if constexpr (DST) {   // p = z = L^{-1} r
-                precondition(rr);
-                double zacc = 0.0;
-                for (int k = tid; k < nodes; k += 1024) {
-                    zacc += (double)rv[k] * (double)zv[k];
-                    pv[k] = zv[k];
-                }
-                rz = block_sum<NW>(zacc, red2);
-            }
             // the inner solve reduces its residual by tol_inner, or only as far as the outer tolerance
             // still needs (a margin of 10 for the Jacobi-scaled norm), whichever is less work
             const double red = fmin(0.5, fmax(a.tol_inner, 0.1 * a.tol64 * fnorm / sqrt(rr64)));
             const double target = red * red * rr;
             bool broke = false;
+            bool have_x = true;   // x holds this sweep's correction (else it is zero)
             if constexpr (DST) {
-                // Per iteration four passes over the global vectors: the stencil (t p of the
-                // neighbours formed on the fly), the x/r update (which also stages fp16(r 2^-ex) for
-                // the transform in LDS), the transform (z stored, r.z accumulated), the p update.
-                // The staged scale comes from the norm before the update (the new one is summed
-                // in the same pass), 2^-3 below unit norm: the residual would have to grow 39-fold
-                // in one iteration to overflow FP16 (the largest intermediate is then below
+                // p = z = L^{-1} r straight from the transform, with r.z summed as z is stored
+                T* pc = pv;    // current search direction
+                T* pn = pv2;   // the next one, written while pc is read (neighbours read pc)
+                double rz = block_sum<NW>(dstg_precondition<DN, T>(rv, pc, Stab, lamtab, 0, norm_exponent(rr) + 3, 1),
+                                          red2);
+                ++napp;
+                // Per iteration three passes over the global vectors: the stencil, which first forms
+                // p <- z + beta p (on the fly at the neighbours too; p is double-buffered because
+                // neighbouring rows read the old one), the x/r update (which also stages fp16(r 2^-ex)
+                // for the transform in LDS), and the transform (z stored, r.z accumulated).  The
+                // staged scale comes from the norm before the update (the new one is summed in the
+                // same pass), 2^-3 below unit norm: the residual would have to grow 39-fold in one
+                // iteration to overflow FP16 (the largest intermediate is then below
                 // 1 / (2 lam_0) / 8 < 1700 times the growth).
+                bool first_it = true;   // p = z as stored, x = 0
+                T beta = T(0);
                 while (rr > target) {
                     if (total >= a.max_iter) break;
                     const int ex = norm_exponent(rr) + 3;
                     const T sc = (T)ldexpf(1.0f, -ex);
                     T pq_acc = T(0);
+                    // p at a node: z + beta p_old (the same fused multiply-add wherever it is formed)
+                    auto pnew = [&](int k) -> T { return first_it ? pc[k] : fma_t(beta, pc[k], zv[k]); };
                     for (int k = 4 * tid; k < nodes; k += 4096) {   // four consecutive nodes of a row
                         const int g = k / NN, c = k % NN;
                         const int kN = (g < NN - 1) ? k + NN : k, kS = (g > 0) ? k - NN : k;
                         const int kW = (c > 0) ? k - 1 : k, kE = min(k + 4, nodes - 1);
-                        const T4 p4 = ld4(pv + k), t4 = ld4(tv + k);
-                        const T4 pN = ld4(pv + kN), tN = ld4(tv + kN);
-                        const T4 pS = ld4(pv + kS), tS = ld4(tv + kS);
-                        const T yW0 = (c > 0) ? tv[kW] * pv[kW] : T(0), yE3 = tv[kE] * pv[kE];
-                        const T p_[4] = {p4.x, p4.y, p4.z, p4.w}, t_[4] = {t4.x, t4.y, t4.z, t4.w};
-                        const T pn[4] = {pN.x, pN.y, pN.z, pN.w}, tn[4] = {tN.x, tN.y, tN.z, tN.w};
+                        T4 p4 = ld4(pc + k), pN = ld4(pc + kN), pS = ld4(pc + kS);
+                        const T4 t4 = ld4(tv + k), tN = ld4(tv + kN), tS = ld4(tv + kS);
+                        if (!first_it) {
+                            const T4 z4 = ld4(zv + k), zN = ld4(zv + kN), zS = ld4(zv + kS);
+                            p4 = fma4(beta, p4, z4);
+                            pN = fma4(beta, pN, zN);
+                            pS = fma4(beta, pS, zS);
+                        }
+                        const T yW0 = (c > 0) ? tv[kW] * pnew(kW) : T(0), yE3 = tv[kE] * pnew(kE);
+                        const T t_[4] = {t4.x, t4.y, t4.z, t4.w};
+                        const T pn_[4] = {pN.x, pN.y, pN.z, pN.w}, tn[4] = {tN.x, tN.y, tN.z, tN.w};
                         const T ps[4] = {pS.x, pS.y, pS.z, pS.w}, ts[4] = {tS.x, tS.y, tS.z, tS.w};
+                        T p_[4] = {p4.x, p4.y, p4.z, p4.w};
                         T yc[4], q_[4];
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) yc[m] = t_[m] * p_[m];
+                        for (int m = 0; m < 4; ++m) {
+                            if (!interior(g, c + m)) p_[m] = T(0);
+                            yc[m] = t_[m] * p_[m];
+                        }
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
                             const T yE = (m < 3) ? yc[m < 3 ? m + 1 : 3] : yE3;
                             const T yW = (m > 0) ? yc[m > 0 ? m - 1 : 0] : yW0;
-                            const T yN = tn[m] * pn[m];
+                            const T yN = tn[m] * pn_[m];
                             const T yS = (g > 0) ? ts[m] * ps[m] : T(0);
                             q_[m] = interior(g, c + m) ? p_[m] - t_[m] * ((yE + yW) + (yN + yS)) : T(0);
                             pq_acc += p_[m] * q_[m];
                         }
+                        if (!first_it) st4(pn + k, p_[0], p_[1], p_[2], p_[3]);
                         st4(qv + k, q_[0], q_[1], q_[2], q_[3]);
                     }
-                    const double pq = block_sum<NW>((double)pq_acc, red1);
-                    if (!(pq > 0.0) || !(pq < INFINITY)) { broke = true; break; }
+                    const double pq = block_sum<NW>((double)pq_acc, red1);   // its barriers publish p and q
+                    if (!first_it) {
+                        T* sw = pc;
+                        pc = pn;
+                        pn = sw;
+                    }
+                    if (!(pq > 0.0) || !(pq < INFINITY)) {
+                        have_x = !first_it;
+                        broke = true;
+                        break;
+                    }
                     const T alpha = (T)(rz / pq);
                     T r_acc = T(0);
                     for (int k = 4 * tid; k < nodes; k += 4096) {
-                        T4 x4 = ld4(xv + k);
-                        const T4 p4 = ld4(pv + k);
+                        const T4 p4 = ld4(pc + k);
+                        T4 x4;
+                        if (first_it) {
+                            x4.x = alpha * p4.x; x4.y = alpha * p4.y; x4.z = alpha * p4.z; x4.w = alpha * p4.w;
+                        } else {
+                            x4 = ld4(xv + k);
+                            x4.x += alpha * p4.x; x4.y += alpha * p4.y; x4.z += alpha * p4.z; x4.w += alpha * p4.w;
+                        }
                         T4 r4 = ld4(rv + k);
                         const T4 q4 = ld4(qv + k);
-                        x4.x += alpha * p4.x; x4.y += alpha * p4.y; x4.z += alpha * p4.z; x4.w += alpha * p4.w;
                         r4.x -= alpha * q4.x; r4.y -= alpha * q4.y; r4.z -= alpha * q4.z; r4.w -= alpha * q4.w;
                         r_acc += ((r4.x * r4.x + r4.y * r4.y) + (r4.z * r4.z + r4.w * r4.w));
                         st4(xv + k, x4.x, x4.y, x4.z, x4.w);
@@ -1107,31 +1144,23 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
                     }
                     rr = block_sum<NW>((double)r_acc, red2);   // its barrier also publishes X
                     ++total;
+                    first_it = false;
                     if (!(rr > target)) break;
-                    double zacc = 0.0;
-                    zacc = dstg_precondition<DN, T>(rv, zv, Stab, lamtab, 1, ex);
+                    double zacc = dstg_precondition<DN, T>(rv, zv, Stab, lamtab, 1, ex, 1);
                     ++napp;
                     double rzn = block_sum<NW>(zacc, red1);
                     if (!(fabs(rzn) < INFINITY)) {   // the residual outgrew the staged scale: redo from r
                         __syncthreads();
-                        zacc = dstg_precondition<DN, T>(rv, zv, Stab, lamtab, 0, norm_exponent(rr) + 3);
-                        double zacc2 = 0.0;
-                        for (int k = tid; k < nodes; k += 1024) zacc2 += (double)rv[k] * (double)zv[k];
-                        rzn = block_sum<NW>(zacc2, red2);
+                        zacc = dstg_precondition<DN, T>(rv, zv, Stab, lamtab, 0, norm_exponent(rr) + 3, 1);
+                        rzn = block_sum<NW>(zacc, red2);
                         ++napp;
                     }
-                    const T beta = (T)(rzn / rz);
+                    beta = (T)(rzn / rz);
                     rz = rzn;
-                    for (int k = 4 * tid; k < nodes; k += 4096) {
-                        const T4 z4 = ld4(zv + k);
-                        T4 p4 = ld4(pv + k);
-                        p4.x = z4.x + beta * p4.x; p4.y = z4.y + beta * p4.y;
-                        p4.z = z4.z + beta * p4.z; p4.w = z4.w + beta * p4.w;
-                        st4(pv + k, p4.x, p4.y, p4.z, p4.w);
-                    }
-                    __syncthreads();
                 }
+                if (first_it) have_x = false;   // no update ran: the correction is zero
             } else {
+            double rz = rr;
             while (rr > target) {
                 if (total >= a.max_iter) break;
                 for (int k = tid; k < nodes; k += 1024) yv[k] = tv[k] * pv[k];
@@ -1170,7 +1199,7 @@ __device__ __forceinline__ void cg_global_body(const SolveArgs& a, const int64_t
             }
             }
             for (int k = tid; k < nodes; k += 1024) {
-                const double corr = sd[k] * (double)xv[k];
+                const double corr = have_x ? (double)sd[k] * (double)xv[k] : 0.0;
                 xo[k] = (sweep == 0) ? corr : xo[k] + corr;
             }
             __syncthreads();
