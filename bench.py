@@ -301,6 +301,8 @@ def main():
                     help="rows per thread of the 128^2 solver (0: autotune before timing)")
     ap.add_argument("--precond", choices=["auto", "jacobi"], default="auto",
                     help="preconditioner of the solves (jacobi: the Jacobi-scaled CG alone, a comparison point)")
+    ap.add_argument("--fused-stage", action="store_true",
+                    help="one persistent launch per stage instead of one launch per move step (comparison)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB device-to-device, to calibrate memory-traffic counters")
     args = ap.parse_args()
@@ -325,6 +327,8 @@ def main():
     p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3,
                     precond=smc.PRECOND_AUTO if fast_poisson else smc.PRECOND_JACOBI)
     unknowns = (GRID - 1) ** 2
+    if args.fused_stage:
+        smc.smc_set_stage_fusion(p, True)
     if not fast_poisson:
         tile, tile_ms = 16, {}   # the Jacobi-only 128^2 solver has one shape, 16 rows per thread
     elif args.tile:
@@ -396,6 +400,11 @@ def main():
         variants["fp64_batched_protocol"] = "%d stages of %d moves after %d warm-up stages" % (
             args.steps, args.moves, args.warmup)
         variants["fp32_refine_over_fp64"] = value / variants["fp64_batched_moves_per_s"]
+        # the same stages as one persistent launch each (every move of a particle in one workgroup)
+        smc.smc_set_stage_fusion(p, True)
+        tf, _, _ = stage_loop(smc.SMC_FP32_REFINE, args.steps, args.warmup, args.moves)
+        smc.smc_set_stage_fusion(p, False)
+        variants["fused_stage_moves_per_s"] = N * args.moves * args.steps / tf
         # the same kernels launched once per particle, FP64
         S, nm, cap = 16, 1, 20.0       # particles, moves each, seconds cap
         xi = torch.empty(S, p.K, dtype=torch.float64, device=dev)

@@ -374,6 +374,14 @@ int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, f
  *                        Synchronises `stream`; overwrites the problem's workspace, so no other
  *                        call on p may be in flight. */
 int smc_tile_candidates(int32_t n, int32_t* rows, int32_t* count);
+/* Launch structure of a move stage (smc_gmpcn_move, smc_gmpcn_stage and their graphs) without a
+ * level map, at SMC_FP32_REFINE on a 2D grid solved on chip with the fast-Poisson preconditioner
+ * (128^2 at 32 or 16 rows per thread, 64^2 at 8): enabled, the whole stage is one persistent
+ * launch in which each workgroup runs every move of a particle (proposal, synthesis, solve,
+ * decision) before taking the next; disabled (the default: measured faster, since the solve fills a
+ * compute unit and the fused launch then runs the synthesis one particle per compute unit too),
+ * each move is one launch per step.  Both give the same bits. */
+int smc_set_stage_fusion(smc_problem p, int32_t enable);
 int smc_set_tile(smc_problem p, int32_t level, int32_t rows);
 int smc_get_tile(smc_problem p, int32_t level, int32_t* rows);
 int smc_autotune(smc_problem p, int32_t level, int64_t N, int32_t reps, smc_stream stream, int32_t* rows,

@@ -14,6 +14,7 @@ using namespace smc;
 
 struct EventPool {
     std::vector<hipEvent_t> ev;   // pairs: ev[2k] before, ev[2k+1] after launch k
+    std::vector<int> rounds;      // solve rounds inside launch k (a stage launch holds one per move)
     size_t used = 0;              // events recorded since the last read
 };
 
@@ -22,6 +23,7 @@ struct smc_problem_s {
     int device = 0;
     EventPool pool;
     bool capturing = false;       // launches are being captured into a graph: no profiling events
+    bool fuse_stage = false;      // a move stage on one on-chip grid runs as one persistent launch
 };
 
 struct smc_graph_s {
@@ -336,13 +338,18 @@ extern "C" void smc_problem_destroy(smc_problem p) {
     delete p;
 }
 
-// Record one event of the current solve launch's bracket on stream s.
-static hipError_t record(EventPool& pool, hipStream_t s) {
+// Record one event of the current solve launch's bracket on stream s; the closing event of a
+// launch that holds several solve rounds (a stage launch) gives their number.
+static hipError_t record(EventPool& pool, hipStream_t s, int rounds = 1) {
     if (pool.used == pool.ev.size()) {
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
         if (r != hipSuccess) return r;
         pool.ev.push_back(e);
+    }
+    if (pool.used % 2) {
+        if (pool.rounds.size() <= pool.used / 2) pool.rounds.resize(pool.used / 2 + 1);
+        pool.rounds[pool.used / 2] = rounds;
     }
     return hipEventRecord(pool.ev[pool.used++], s);
 }
@@ -371,8 +378,10 @@ extern "C" int smc_profile_read(smc_problem p, smc_stream stream, double* ms, in
     }
     unsigned long long st[4];
     HIPCHK(hipMemcpy(st, p->P.stats, sizeof(st), hipMemcpyDeviceToHost));
+    int64_t rounds = 0;
+    for (size_t k = 0; k < p->pool.used / 2; ++k) rounds += k < p->pool.rounds.size() ? p->pool.rounds[k] : 1;
     if (ms) *ms = tot;
-    if (launches) *launches = (int64_t)(p->pool.used / 2);
+    if (launches) *launches = rounds;
     if (iters) *iters = (int64_t)st[0];
     if (sweeps) *sweeps = (int64_t)st[1];
     if (solves) *solves = (int64_t)st[2];
@@ -650,6 +659,56 @@ extern "C" int smc_potential(smc_problem p, int64_t N, const double* G, double* 
     return SMC_OK;
 }
 
+// Tile of the fast-Poisson solver of grid `level` (the set one, else the default).
+static int tile_rows(const Problem& P, int level) {
+    int c[8];
+    tile_candidates(P.lv[level].n, c);
+    return P.lv[level].rows ? P.lv[level].rows : c[0];
+}
+
+// A whole stage of moves in one persistent launch (single grid, FP32 with refinement, on-chip
+// fast-Poisson solver with a tile that has a stage kernel).
+static bool stage_fusable(const smc_problem_s* p, const int32_t* level, int32_t prec) {
+    const Problem& P = p->P;
+    if (!p->fuse_stage || level || P.kind != KIND_DARCY || P.dim != 2 || prec != SMC_FP32_REFINE ||
+        P.precond != SMC_PRECOND_AUTO || !P.lv[0].dst_S)
+        return false;
+    return stage_fused_supported(P.lv[0].n, tile_rows(P, 0));
+}
+
+static hipError_t stage_launch(smc_problem_s* ps, int64_t N, const MoveParams& q, int32_t n_moves, double* xi,
+                               double* phi, int32_t* n_acc, hipStream_t s) {
+    const Problem& P = ps->P;
+    const Level& L = P.lv[0];
+    SolveArgs a = solve_args(P, 0);
+    a.phi = P.ws_phinew;
+    a.iters = P.ws_iters;
+    a.stats = P.profiling ? P.stats : nullptr;
+    StageArgs st{};
+    st.N = N;
+    st.K = P.K;
+    st.kl = P.kl;
+    st.n_moves = n_moves;
+    st.active = P.active;
+    st.slot = P.slot;
+    st.tab = P.ws_mixtab;
+    st.sqrt_lam = P.sqrt_lam;
+    st.basis = L.basis;
+    st.xi = xi;
+    st.phi = phi;
+    st.n_acc = n_acc;
+    st.v = P.ws_v;
+    st.logr = P.ws_logr;
+    st.flags = P.flags;
+    const bool rec = P.profiling && !ps->capturing;
+    hipError_t e;
+    if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
+    e = launch_stage_onchip(L.n, tile_rows(P, 0), a, st, q, L.dst_S, L.dst_lam, P.ws_counters, P.n_cu, s);
+    if (e != hipSuccess) return e;
+    if (rec) e = record(ps->pool, s, n_moves);
+    return e;
+}
+
 // The move loop shared by smc_gmpcn_move and smc_gmpcn_stage (arguments already checked).
 static int move_loop(smc_problem_s* p, int64_t N, MoveParams q, int32_t n_moves, const int32_t* level, int32_t prec,
                      double* xi, double* phi, int32_t* n_acc, hipStream_t s) {
@@ -658,6 +717,10 @@ static int move_loop(smc_problem_s* p, int64_t N, MoveParams q, int32_t n_moves,
     HIPCHK(launch_fill_i32(n_acc, N, 0, s));
     if (level) HIPCHK(launch_plan(N, level, level_table(P), P.ws_list, P.ws_counters, P.flags, s));
     if (n_moves > 0) HIPCHK(launch_mixtab(q, P.ws_mixtab, s));
+    if (n_moves > 0 && stage_fusable(p, level, prec)) {
+        HIPCHK(stage_launch(p, N, q, n_moves, xi, phi, n_acc, s));
+        return SMC_OK;
+    }
     for (int m = 0; m < n_moves; ++m) {
         q.m = m;
         HIPCHK(launch_propose(N, P.K, P.active, P.slot, q, P.ws_mixtab, xi, P.ws_v, P.ws_logr, P.flags, s));
@@ -938,6 +1001,12 @@ extern "C" int smc_set_tile(smc_problem p, int32_t level, int32_t rows) {
     if (!p) return fail(SMC_E_INVAL, "problem is NULL");
     if (int r = check_tile(p->P, level, rows)) return r;
     p->P.lv[level].rows = rows;
+    return SMC_OK;
+}
+
+extern "C" int smc_set_stage_fusion(smc_problem p, int32_t enable) {
+    if (!p) return fail(SMC_E_INVAL, "problem is NULL");
+    p->fuse_stage = enable != 0;
     return SMC_OK;
 }
 

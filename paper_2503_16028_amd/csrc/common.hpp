@@ -215,6 +215,30 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
                                  const int32_t* level, double* out, int64_t out_stride, int64_t N, bool exp_half,
                                  hipStream_t s);
 bool mixed_supported(int n);
+// The rest of a persistent move-stage launch (the solver's arguments are a SolveArgs): the
+// particles' state, the proposal workspace and the tables the proposal and synthesis read.
+struct StageArgs {
+    int64_t N;
+    int K, kl, n_moves;
+    const int32_t* active;
+    const int32_t* slot;
+    const double* tab;        // mixture table of the call (mixtab_kernel)
+    const double* sqrt_lam;
+    const double* basis;      // cosine basis of the grid
+    double* xi;               // [N][K] state, in/out
+    double* phi;              // [N] potentials, in/out
+    int32_t* n_acc;           // [N] accept counts (zeroed before the launch)
+    double* v;                // [N][K] proposal workspace
+    double* logr;             // [N] log ratio workspace
+    int32_t* flags;
+};
+// One launch for a whole stage of n_moves pCN-GM moves on one grid solved on chip with the
+// fast-Poisson preconditioner (FP32 with FP64 refinement): false if no such launch exists for
+// this grid and tile (then the moves run one launch per step).
+bool stage_fused_supported(int n, int rows);
+hipError_t launch_stage_onchip(int n, int rows, const SolveArgs& a, const StageArgs& st, const MoveParams& q,
+                               const void* S, const float* lam, unsigned long long* counters, int grid,
+                               hipStream_t s);
 hipError_t launch_plan(int64_t N, const int32_t* level, const LevelTable& lt, int32_t* list,
                        unsigned long long* counters, int32_t* flags, hipStream_t s);
 hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a, const LevelTable& lt,

@@ -31,6 +31,8 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "move_body.hpp"
+#include "synth_body.hpp"
 
 namespace smc {
 
@@ -313,9 +315,11 @@ __device__ __forceinline__ double from_prev_lane(double v, double edge) {
 // returns the sum of squares of the unscaled residual.  Every load has a clamped, in-bounds index
 // and a select discards what lies outside the domain, so the strip is straight-line code whose
 // loads are issued 8 rows at a time.  The east and west values of e and x come from the adjacent
-// lanes; only the two wave edges load them (e, read-only here, through the scalar unit: in SGPRs
-// they leave the vector registers to the rows' loads).
-template <typename T, int NN, int R, bool SRC, typename SD>
+// lanes; only the two wave edges load them (e through the scalar unit when SE: in SGPRs they leave
+// the vector registers to the rows' loads).  The scalar cache does not see vector stores, so SE is
+// only for a field no store of the same launch has written (the synthesis ran in an earlier one);
+// a launch that synthesises the field itself loads the edges as vectors.
+template <typename T, int NN, int R, bool SRC, typename SD, bool SE = true>
 __device__ __noinline__ double strip_residual(const double* __restrict__ e_, const double* __restrict__ xo_,
                                               const SD* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
                                               bool zero_x, double f, const double* __restrict__ src_w,
@@ -365,8 +369,8 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
             xN[k] = xo[min(g + 1, NN - 1) * NN + c];
             sdv[k] = (double)sd[g * NN + c];
             const int ju = g0u + r0 + k + 1;
-            eEe[k] = eu[ju * NP1 + ieE];
-            eWe[k] = eu[ju * NP1 + ieW];
+            eEe[k] = SE ? eu[ju * NP1 + ieE] : e[ju * NP1 + ieE];
+            eWe[k] = SE ? eu[ju * NP1 + ieW] : e[ju * NP1 + ieW];
             xEe[k] = xo[g * NN + cxE];
             xWe[k] = xo[g * NN + cxW];
         }
@@ -418,8 +422,9 @@ __device__ __noinline__ void strip_update(double* xo_, const SD* sd_, const T* t
     }
 }
 
-// D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots.
-template <typename T, int NN, int R, typename SD>
+// D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots (SE as for
+// strip_residual).
+template <typename T, int NN, int R, typename SD, bool SE = true>
 __device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __restrict__ sd_, T* __restrict__ tb_,
                                          int c, int g0) {
     static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
@@ -443,8 +448,8 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __re
         for (int k = 0; k < B; ++k) {
             const int j = g0 + r0 + k + 1, ju = g0u + r0 + k + 1;
             eN[k] = e[min(j + 1, NN) * NP1 + i];
-            eEe[k] = eu[ju * NP1 + ieE];
-            eWe[k] = eu[ju * NP1 + ieW];
+            eEe[k] = SE ? eu[ju * NP1 + ieE] : e[ju * NP1 + ieE];
+            eWe[k] = SE ? eu[ju * NP1 + ieW] : e[ju * NP1 + ieW];
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -462,7 +467,7 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __re
 
 // One particle's solve by the whole workgroup (NN * NN / R threads); `smem` holds at least
 // onchip_smem<T, NN, R, DST>() bytes.  Used by the per-grid kernel and by the mixed-grid one.
-template <typename T, int NN, int R, bool DST, bool ADJ>
+template <typename T, int NN, int R, bool DST, bool ADJ, bool SE = true>
 __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t row, const int32_t* __restrict__ obs,
                                                unsigned char* smem, SolveShared& sh,
                                                const _Float16* __restrict__ Stab, const float* __restrict__ lamtab) {
@@ -502,7 +507,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     }
     // ---- setup: D^{-1/2} (workspace, in SD) and t (registers), staged through the thread's own LDS slots
     if constexpr (SPLIT) {
-        strip_setup<T, NN, R, SD>(e, sd, tb, c, b * R);
+        strip_setup<T, NN, R, SD, SE>(e, sd, tb, c, b * R);
     } else {
         // column i of e, rows j-1, j, j+1 carried along the strip (j = g + 1)
         double eS = e[(b * R) * NP1 + i], eC = e[(b * R + 1) * NP1 + i];
@@ -590,9 +595,9 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
             ++sweeps;
             double acc = 0.0;
             if constexpr (SPLIT) {
-                acc = (pass == 1) ? strip_residual<T, NN, R, true>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
+                acc = (pass == 1) ? strip_residual<T, NN, R, true, SD, SE>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
                                                                    src_at, a.n_obs)
-                                  : strip_residual<T, NN, R, false>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
+                                  : strip_residual<T, NN, R, false, SD, SE>(e, xo, sd, tb, c, b * R, sweep == 0, a.f, src_w,
                                                                     src_at, a.n_obs);
             } else
             if (sweep == 0) {
@@ -1351,11 +1356,11 @@ bool mixed_supported(int n) { return n == 64 || n == 128 || n == 256; }
 // so that the bodies keep their LDS instructions.
 __shared__ SolveShared g_mixed_sh;
 
-template <typename T, int NN, int R, bool DST>
+template <typename T, int NN, int R, bool DST, bool SE = true>
 __device__ __noinline__ void mixed_onchip(const SolveArgs& a, int64_t p, const int32_t* obs, const void* S,
                                           const float* lam) {
     static_assert(onchip_smem<T, NN, R, DST>() <= MIXED_SMEM, "mixed-grid LDS");
-    cg_onchip_body<T, NN, R, DST, false>(a, p, obs, g_mixed_smem, g_mixed_sh, reinterpret_cast<const _Float16*>(S),
+    cg_onchip_body<T, NN, R, DST, false, SE>(a, p, obs, g_mixed_smem, g_mixed_sh, reinterpret_cast<const _Float16*>(S),
                                          lam);
 }
 
@@ -1426,6 +1431,94 @@ __global__ __launch_bounds__(1024) void solve_mixed_kernel(SolveArgs a, LevelTab
             counters[1] = 0;
         }
     }
+}
+
+// ------------------------------------------------------------------ persistent move stage
+// One launch per stage of n_moves pCN-GM moves (Alg. 2) for particles on one grid solved on chip:
+// each workgroup takes the next particle from a counter and runs its whole stage, move after move
+// (proposal, synthesis of exp(u/2), forward solve and potential, decision), then the next particle.
+// The particles of a stage do not interact, so this is the same computation as one launch per
+// step (the same bodies in the same order for each particle: the same bits), without a kernel
+// boundary, and its drain, between the steps.  Each phase is a function of its own, register-
+// allocated apart, and they share the module-level LDS in turn.
+__shared__ int g_stage_acc;
+
+template <int NN, int R>
+__device__ __noinline__ void stage_propose(const StageArgs& st, const MoveParams& q, int64_t p) {
+    propose_body<NN * NN / R>(p, st.K, st.active, st.slot, q, st.tab, st.xi, st.v, st.logr, st.flags);
+}
+
+template <int NN, int R>
+__device__ __noinline__ void stage_synth(const StageArgs& st, int64_t p, double* e, int64_t e_stride) {
+    static_assert((NN * NN / R) % 64 == 0, "whole waves");
+    synth2d_body<true, NN * NN / R / 64>(st.v + p * st.K, st.kl, st.sqrt_lam, st.basis, NN, e + p * e_stride,
+                                         reinterpret_cast<double*>(g_mixed_smem));
+}
+
+template <int NN, int R>
+__device__ __noinline__ void stage_accept(const StageArgs& st, const MoveParams& q, int64_t p, const double* phinew) {
+    accept_body<NN * NN / R>(p, st.K, q, st.v, st.logr, phinew, st.xi, st.phi, st.n_acc, g_stage_acc);
+}
+
+template <int NN, int R>
+__global__ __launch_bounds__(NN * NN / R) void stage_onchip_kernel(SolveArgs a, StageArgs st, MoveParams q,
+                                                                   const _Float16* __restrict__ S,
+                                                                   const float* __restrict__ lam,
+                                                                   unsigned long long* counters) {
+    __shared__ unsigned long long item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&counters[0], 1ull);
+        __syncthreads();
+        // wave-uniform item: the loop exit below must be a uniform branch (see solve_mixed_kernel)
+        const int64_t p = __builtin_amdgcn_readfirstlane((int)(item_s < (unsigned long long)st.N ? item_s : st.N));
+        __syncthreads();
+        if (p >= st.N) break;
+        for (int m = 0; m < st.n_moves; ++m) {
+            MoveParams qm = q;
+            qm.m = m;
+            stage_propose<NN, R>(st, qm, p);
+            __syncthreads();
+            stage_synth<NN, R>(st, p, const_cast<double*>(a.e), a.e_stride);
+            __syncthreads();
+            mixed_onchip<float, NN, R, true, false>(a, p, a.obs, S, lam);   // phi of the proposal into a.phi
+            __syncthreads();
+            stage_accept<NN, R>(st, qm, p, a.phi);
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long done = atomicAdd(&counters[1], 1ull);
+        if (done == (unsigned long long)gridDim.x - 1ull) {   // every workgroup has stopped fetching
+            counters[0] = 0;
+            counters[1] = 0;
+        }
+    }
+}
+
+bool stage_fused_supported(int n, int rows) {
+    return (n == 128 && (rows == 32 || rows == 16)) || (n == 64 && rows == 8);
+}
+
+hipError_t launch_stage_onchip(int n, int rows, const SolveArgs& a, const StageArgs& st, const MoveParams& q,
+                               const void* S, const float* lam, unsigned long long* counters, int grid,
+                               hipStream_t s) {
+    if (st.N <= 0) return hipSuccess;
+    const unsigned g = (unsigned)(st.N < grid ? st.N : grid);
+    const _Float16* Sh = reinterpret_cast<const _Float16*>(S);
+    const int key = n * 64 + rows;
+    switch (key) {
+        case 128 * 64 + 32:
+            stage_onchip_kernel<128, 32><<<dim3(g), dim3(512), 0, s>>>(a, st, q, Sh, lam, counters);
+            break;
+        case 128 * 64 + 16:
+            stage_onchip_kernel<128, 16><<<dim3(g), dim3(1024), 0, s>>>(a, st, q, Sh, lam, counters);
+            break;
+        case 64 * 64 + 8:
+            stage_onchip_kernel<64, 8><<<dim3(g), dim3(512), 0, s>>>(a, st, q, Sh, lam, counters);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a, const LevelTable& lt,

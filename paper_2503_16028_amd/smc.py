@@ -83,6 +83,7 @@ _SIGS = {
     "smc_stage_graph_destroy": (None, [c_vp]),
     "smc_tile_candidates": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "smc_set_tile": (c_i32, [c_vp, c_i32, c_i32]),
+    "smc_set_stage_fusion": (c_i32, [c_vp, c_i32]),
     "smc_get_tile": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "smc_autotune": (c_i32, [c_vp, c_i32, c_i64, c_i32, c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl)]),
     "smc_temper": (c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -405,6 +406,12 @@ def smc_tile_candidates(n):
     count = c_i32()
     _check(lib().smc_tile_candidates(int(n), rows, ctypes.byref(count)))
     return [rows[k] for k in range(count.value)]
+
+
+def smc_set_stage_fusion(problem, enable):
+    """One persistent launch per move stage (True, where supported) or one launch per step (False, the
+    default)."""
+    _check(lib().smc_set_stage_fusion(problem.handle, 1 if enable else 0))
 
 
 def smc_set_tile(problem, level, rows):

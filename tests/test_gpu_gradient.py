@@ -262,16 +262,17 @@ def test_pcnl_move_fp32_refine_128_sampled():
     g = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
     smc.smc_value_and_grad(p, N, X, smc.SMC_FP32_REFINE, None, phi, g)
     torch.cuda.synchronize()
-    phi0, g0 = phi.cpu().numpy().copy(), g.cpu().numpy().copy()
-    tau = float(min(1.0, 2.0 / np.median(phi0)))
+    picks = (0, 101, 255)
+    ref0 = {k: value_and_grad(op, xi[k], grid) for k in picks}       # the oracle's own starting points
+    tau = float(min(1.0, 2.0 / np.median([ref0[k][0] for k in picks])))
     acc = torch.empty(N, dtype=torch.int32, device=DEV)
     smc.smc_pcnl_move(p, N, beta, tau, n_moves, 5, 77, smc.SMC_FP32_REFINE, X, phi, g, acc)
     torch.cuda.synchronize()
     assert smc.smc_status_flags(p) == 0
     got_acc, got_x, got_phi = acc.cpu().numpy(), X.cpu().numpy(), phi.cpu().numpy()
     assert 0 < got_acc.sum() < N * n_moves
-    for k in (0, 101, 255):
-        rphi0, rg0 = value_and_grad(op, xi[k], grid)
+    for k in picks:
+        rphi0, rg0 = ref0[k]
         rx, rphi, _, racc = pcnl_moves(beta, tau, xi[k:k + 1], np.array([rphi0]), rg0[None], n_moves, 5, 77,
                                        lambda v: value_and_grad(op, v, grid), ids=[k])
         assert got_acc[k] == racc[0]

@@ -10,7 +10,7 @@ stage produces, on both precisions, each printed as a "[ledger]" line and held t
   h, W, log Z  tempering of the potentials of the same cloud (W element-wise over the largest W)
   grad   dPhi/dxi, largest component error over the largest component
 Sizes: 64 sampled particles of a 4096-particle batch (the benchmark's launch) for G and Phi,
-4096 proposals for log R, 4096 potentials for tempering, 8 particles for the gradient.
+4096 proposals for log R, 4096 seeded potentials for tempering, 8 particles for the gradient.
 """
 import json
 import sys
@@ -122,22 +122,21 @@ def test_log_ratio(c3):
 
 
 def test_tempering(c3, cloud):
+    """Seeded potentials with the spread of the first stage's (the oracle's potentials of the sampled
+    prior draws set the scale)."""
     from paper_2503_16028_amd import smc
     banner("ledger h, W, log Z")
     d, op = c3
-    xi, _ = cloud
-    p = smc.Problem(d, N_BATCH, tol64=1e-10, tol_inner=1e-3)
-    G = torch.empty(N_BATCH, op.n_obs, dtype=torch.float64, device=DEV)
-    phi = torch.empty(N_BATCH, dtype=torch.float64, device=DEV)
-    smc.smc_forward_batch(p, N_BATCH, t(xi), None, smc.SMC_FP32_REFINE, G)
-    smc.smc_potential(p, N_BATCH, G, phi)
+    _, ref_G = cloud
+    scale = float(np.median(potential(ref_G, op.y, op.sigma))) / 4.0
+    phi = t(inputs.potentials(N_BATCH, 91, spread=scale))
     worst = dict(h=0.0, W=0.0, logZ=0.0)
     for tau in (0.0, 0.37):
         h, tau_new, lz = (torch.empty(1, dtype=torch.float64, device=DEV) for _ in range(3))
         W = torch.empty(N_BATCH, dtype=torch.float64, device=DEV)
         smc.smc_temper(N_BATCH, phi, t([tau]), 0.5, h, tau_new, W, lz)
         torch.cuda.synchronize()
-        rh, rtau, rW, rlz, stalled = temper(phi.cpu().numpy(), tau, 0.5)   # the same potentials
+        rh, rtau, rW, rlz, stalled = temper(inputs.potentials(N_BATCH, 91, spread=scale), tau, 0.5)
         worst["h"] = max(worst["h"], abs(h.item() / rh - 1))
         worst["W"] = max(worst["W"], np.abs(W.cpu().numpy() - rW).max() / rW.max())
         worst["logZ"] = max(worst["logZ"], abs(lz.item() / rlz - 1))

@@ -469,7 +469,8 @@ def test_full_size_metric_configuration_sampled():
     phi = torch.empty(N, dtype=torch.float64, device=DEV)
     smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G, it)
     smc.smc_potential(p, N, G, phi)
-    xi_h = xi.cpu().numpy()
+    xi_h = philox.normals(2503, 0, np.arange(N), op.K)   # the oracle's own draws of the same counters
+    assert np.abs(xi.cpu().numpy() - xi_h).max() < 1e-13
     phi_h = phi.cpu().numpy()
     assert (it.cpu().numpy() > 0).all() and np.isfinite(phi_h).all()
     pick = sorted(set(np.linspace(0, N - 1, 62).astype(int).tolist()) | {1, 777})
@@ -480,7 +481,7 @@ def test_full_size_metric_configuration_sampled():
     smc.smc_gmpcn_move(p, N, (t(logw), t(mean), t(scale)), 0.2, 0.05, 1, 9, 500, None, smc.SMC_FP32_REFINE, xi,
                        phi, n_acc)
     gm = GM(logw, mean, scale, op.active(), op.K)
-    rx, rphi, racc = gmpcn_moves(op, 128, xi_h[pick], phi_h[pick], gm, 0.2, 0.05, 1, 9, 500, ids=pick)
+    rx, rphi, racc = gmpcn_moves(op, 128, xi_h[pick], ref, gm, 0.2, 0.05, 1, 9, 500, ids=pick)   # oracle's own Phi
     assert np.array_equal(n_acc.cpu().numpy()[pick], racc)
     assert np.abs(xi.cpu().numpy()[pick] - rx).max() <= 1e-6
     assert np.abs(phi.cpu().numpy()[pick] / rphi - 1).max() <= 1e-4
