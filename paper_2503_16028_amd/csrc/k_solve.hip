@@ -278,6 +278,13 @@ template <typename S> using gp = __attribute__((address_space(1))) S*;
 // kernel writes while it runs (the coefficient field, written by the synthesis launch before).
 typedef const __attribute__((address_space(4))) double* kcdp;
 
+// The adjoint's point sources (G - y) / sigma^2 of the on-chip solver: weights and interior flat
+// indices (-1: not an interior node), written by the forward pass's observation.  Named at module
+// level so that the residual pass, a function of its own, reads them with LDS instructions (through a
+// pointer argument they would become generic accesses).
+__shared__ double g_src_w[MAX_OBS];
+__shared__ int g_src_at[MAX_OBS];
+
 // Right-hand side of the pass at interior unknown `flat`: f, or the adjoint's point sources.
 __device__ __forceinline__ double strip_rhs(int flat, bool sources, double f, const double* src_w, const int* src_at,
                                             int n_obs) {
@@ -334,12 +341,49 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
     const int i = c + 1;
     const bool colin = c < NN - 1;
     double acc = 0.0;
+    // SRC: the sources in this thread's strip (column c, rows g0 .. g0 + R - 1), found once; a strip
+    // with more than SMAX of them sums over every source at each row instead
+    constexpr int SMAX = 4;
+    int srow[SMAX];
+    double sw[SMAX];
+    int ns = 0;
+    if constexpr (SRC) {
+#pragma unroll
+        for (int q = 0; q < SMAX; ++q) {
+            srow[q] = -1;
+            sw[q] = 0.0;
+        }
+        for (int k = 0; k < n_obs; ++k) {
+            const int at = g_src_at[k];
+            const int gr = at / NN, cc = at - gr * NN;
+            if (at >= 0 && cc == c && gr >= g0 && gr < g0 + R) {
+#pragma unroll
+                for (int q = 0; q < SMAX; ++q)
+                    if (q == ns) {
+                        srow[q] = gr - g0;
+                        sw[q] = g_src_w[k];
+                    }
+                ++ns;
+            }
+        }
+    }
+    auto rhs_at = [&](int r) -> double {
+        if constexpr (!SRC) {
+            return f;
+        } else {
+            if (ns > SMAX) return strip_rhs((g0 + r) * NN + c, true, f, g_src_w, g_src_at, n_obs);
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < SMAX; ++q) v += (srow[q] == r) ? sw[q] : 0.0;
+            return v;
+        }
+    };
     if (zero_x) {
 #pragma unroll 8
         for (int r = 0; r < R; ++r) {
             const int g = g0 + r;
             const bool in = colin && g < NN - 1;
-            const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
+            const double fr = rhs_at(r);
             const double sdv = (double)sd[g * NN + c];
             acc += in ? fr * fr : 0.0;
             tb[NN + 1 + r * NN] = in ? (T)(sdv * fr) : T(0);
@@ -385,7 +429,7 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
             const double xe = (c + 1 < NN - 1) ? xe_ : 0.0;
             const double xw = (c > 0) ? xw_ : 0.0;
             const bool in = colin && g < NN - 1;
-            const double fr = SRC ? strip_rhs(g * NN + c, true, f, src_w, src_at, n_obs) : f;
+            const double fr = rhs_at(r);
             const double res = fr - eC * inv_h2 * (eE * (xC - xe) + eW * (xC - xw) + eN[k] * (xC - xn) + eS * (xC - xS));
             acc += in ? res * res : 0.0;
             tb[NN + 1 + r * NN] = in ? (T)(sdv[k] * res) : T(0);
@@ -467,10 +511,18 @@ __device__ __noinline__ void strip_setup(const double* __restrict__ e_, SD* __re
 
 // One particle's solve by the whole workgroup (NN * NN / R threads); `smem` holds at least
 // onchip_smem<T, NN, R, DST>() bytes.  Used by the per-grid kernel and by the mixed-grid one.
-template <typename T, int NN, int R, bool DST, bool ADJ, bool SE = true>
+template <typename T, int NN, int R, bool DST, bool ADJ, bool SE = true, bool AONLY = false>
 __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t row, const int32_t* __restrict__ obs,
                                                unsigned char* smem, SolveShared& sh,
                                                const _Float16* __restrict__ Stab, const float* __restrict__ lamtab) {
+    // AONLY: the adjoint problem alone, the forward solution already in x64 from an earlier launch
+    // (whose iteration count, or -1 for a failed solve, is in iters unless the caller gave w)
+    static_assert(!AONLY || ADJ, "adjoint-only needs the adjoint pass");
+    int prev_iters = 0;
+    if constexpr (AONLY) {
+        prev_iters = (a.iters && !a.fwd_given) ? __builtin_amdgcn_readfirstlane(a.iters[row]) : 0;
+        if (prev_iters < 0) return;   // no forward solution: the row keeps iters = -1 (gradient NaN)
+    }
     constexpr int NT = NN * NN / R;
     constexpr int NW = NT / 64;
     constexpr int NP1 = NN + 1;
@@ -482,8 +534,8 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     constexpr bool SPLIT = R >= 32;
     double* red1 = sh.red1;
     double* red2 = sh.red2;
-    double* src_w = sh.src_w;
-    int* src_at = sh.src_at;
+    double* src_w = g_src_w;   // module-level: the residual function reads them by name
+    int* src_at = g_src_at;
     T* ly = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -573,13 +625,13 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
 
     // ---- pass 0: forward problem A w = f into x64 (skipped when x64 already holds w);
     //      pass 1 (ADJ): adjoint problem A lam = P^T (P w - y) / sigma^2 into a.lam
-    const int first = (ADJ && a.fwd_given) ? 1 : 0, last = ADJ ? 1 : 0;
+    const int first = (ADJ && (AONLY || a.fwd_given)) ? 1 : 0, last = ADJ ? 1 : 0;
     int total = 0, sweeps = 0, solves = 0;
     bool ok = true;
     T x[R], rv[R], p[R], q[R];
 #pragma unroll 1
     for (int pass_ = first; pass_ <= last && ok; ++pass_) {
-        const int pass = ADJ ? pass_ : 0;
+        const int pass = AONLY ? 1 : (ADJ ? pass_ : 0);
         if (pass == 1 && first == 1) observe(true);
         double* xo = pass ? a.lam + row * a.lam_stride : x64;
         auto rhs = [&](int flat) __attribute__((always_inline)) -> double {
@@ -761,7 +813,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
 
     // ---- bookkeeping
     if (tid == 0) {
-        if (a.iters) a.iters[row] = ok ? total : -1;
+        if (a.iters) a.iters[row] = ok ? prev_iters + total : -1;
         if (!ok) atomicOr(a.flags, SMC_FLAG_NOCONV);
         if (a.stats) {
             atomicAdd(&a.stats[0], (unsigned long long)total);
@@ -773,12 +825,12 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
     __syncthreads();   // the next body may reuse the LDS
 }
 
-template <typename T, int NN, int R, bool DST, bool ADJ>
+template <typename T, int NN, int R, bool DST, bool ADJ, bool AONLY = false>
 __global__ __launch_bounds__(NN * NN / R) void cg_onchip(SolveArgs a, const _Float16* __restrict__ Stab,
                                                          const float* __restrict__ lamtab) {
     __shared__ __align__(16) unsigned char smem[onchip_smem<T, NN, R, DST>()];
     __shared__ SolveShared sh;
-    cg_onchip_body<T, NN, R, DST, ADJ>(a, blockIdx.x, a.obs, smem, sh, Stab, lamtab);
+    cg_onchip_body<T, NN, R, DST, ADJ, true, AONLY>(a, blockIdx.x, a.obs, smem, sh, Stab, lamtab);
 }
 
 // Same method (Jacobi-scaled CG, product form) with every vector in global memory, for grids
@@ -1552,6 +1604,21 @@ static hipError_t run_onchip(int64_t N, const SolveArgs& a, const void* S, const
     return hipGetLastError();
 }
 
+// Forward and adjoint solves as two launches of the forward solver's shape (a body with both passes
+// needs more registers than the 32-row shape has): the forward problem into x64, then the adjoint
+// problem alone from it; the second launch adds its iterations to the first's.
+template <typename T, int NN, int R>
+static hipError_t run_onchip_two_pass(int64_t N, const SolveArgs& a, const void* S, const float* lam, hipStream_t s) {
+    const _Float16* Sb = reinterpret_cast<const _Float16*>(S);
+    if (!a.fwd_given) {
+        SolveArgs f = a;
+        f.lam = nullptr;
+        cg_onchip<T, NN, R, true, false><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(f, Sb, lam);
+    }
+    cg_onchip<T, NN, R, true, true, true><<<dim3((unsigned)N), dim3(NN * NN / R), 0, s>>>(a, Sb, lam);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t run_global(int64_t N, const SolveArgs& a, int n, hipStream_t s) {
     if (a.lam)
@@ -1578,9 +1645,9 @@ int tile_candidates(int n, int* rows) {
 hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, const void* S, const float* lam,
                               hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    // the default shape of the forward-and-adjoint solve at 128^2 is 16 rows per thread: with the
-    // second pass the 32-row shape no longer fits its registers (measured slower)
-    if (a.lam && rows == 0 && n == 128) rows = 16;
+    // forward and adjoint at 128^2 in the 32-row shape: two launches (one body with both passes
+    // spills at 32 rows; 16 rows runs both passes in one launch)
+    if (a.lam && n == 128 && (rows == 0 || rows == 32)) return run_onchip_two_pass<float, 128, 32>(N, a, S, lam, s);
     const int key = n * 64 + rows;
     switch (key) {
         case 32 * 64 + 0:
