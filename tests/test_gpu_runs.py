@@ -20,8 +20,12 @@ choice, normals, acceptance uniform), so:
     and moves is taken to carry the information of N / 4 independent draws (the effective size
     used throughout these tests); then for every active coordinate
       |mean_gpu - mean_oracle| <= 4.5 s sqrt(4 / N_gpu + 4 / N_oracle),
-      |std_gpu / std_oracle - 1| <= 4.5 sqrt(2 / N_gpu + 2 / N_oracle),
-    and log Z within LOGZ_TOL (4.5 times the seed-to-seed spread of log Z measured at N = 1024).
+      |std_gpu / std_oracle - 1| <= 4.5 sqrt(2 / N_gpu + 2 / N_oracle).
+  * log Z at equal N: the estimate of log Z depends on N beyond its spread (measured on the GPU over
+    8 seeds: mean -17.68, standard deviation 0.13 at N = 1024; -17.31, 0.06 at N = 4096, a downward
+    bias of the logarithm of an unbiased estimate that shrinks as N grows), so the oracle's N = 1024
+    log Z is held against 8 GPU runs of N = 1024 from other seeds:
+      |log Z_oracle - mean| <= 4.5 sd sqrt(1 + 1/8).
 """
 import json
 import math
@@ -35,7 +39,6 @@ from conftest import golden
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-LOGZ_TOL = 0.5
 
 
 def banner(*a):
@@ -130,4 +133,16 @@ def test_c3_metric_configuration_posterior_moments():
     assert g["taus"][-1] == 1.0
     assert z_mean.max() <= 4.5, z_mean
     assert z_std.max() <= 4.5, z_std
-    assert abs(g["log_Z"] - ref["log_Z"]) <= LOGZ_TOL
+
+
+def test_c3_log_evidence_against_runs_from_other_seeds():
+    """The oracle's log Z (N = 1024) within Monte Carlo spread of 8 GPU runs of N = 1024, FP32 with
+    refinement at the benchmark's tolerances, seeds 1..8 (module docstring)."""
+    from paper_2503_16028_amd import smc
+    banner("c3 log Z across seeds")
+    d, ref = load("c3")
+    lz = np.array([gpu_run(d, ref, ref["N"], smc.SMC_FP32_REFINE, 1e-10, 1e-3, seed=s)["log_Z"] for s in range(1, 9)])
+    sd = lz.std(ddof=1)
+    print("[measured] log Z over seeds: mean %.4f sd %.4f; oracle %.4f (z %.2f)" %
+          (lz.mean(), sd, ref["log_Z"], abs(ref["log_Z"] - lz.mean()) / (sd * math.sqrt(1 + 1 / 8))), flush=True)
+    assert abs(ref["log_Z"] - lz.mean()) <= 4.5 * sd * math.sqrt(1 + 1 / 8)
