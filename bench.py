@@ -24,6 +24,21 @@ FLOPS_PER_UNKNOWN_SWEEP = 16    # one FP64 residual evaluation per interior unkn
 FP32_VECTOR_PEAK = 157.3e12     # MI355X published FP32 vector peak
 F16_MFMA_PEAK = 2.5e15          # MI355X published dense fp16 and bf16 matrix peak
 HBM_PEAK = 8.0e12               # MI355X HBM3E peak, bytes/s
+LDS_PEAK = 256 * 128 * 2.4e9    # LDS bandwidth: 256 compute units x 128 bytes per clock x 2.4 GHz
+
+
+def lds_bytes_per_solve(iters, apps, sweeps, n=GRID):
+    """LDS bytes one 128^2 on-chip solve moves (32 rows per thread), from the kernel's access pattern:
+    per preconditioner application the FP16 staging of r (2 n^2 bytes), four products that each read
+    their FP16 operand once per strip group (4 groups: 8 n^2), three FP16 results (2 n^2 each), the
+    FP32 result (4 n^2) and the solver reading it back (4 n^2); per CG iteration the published t p
+    (4 n^2) and its four neighbour reads (16 n^2); per FP64 sweep the residual and the update through
+    the strip's FP32 LDS slots (16 n^2)."""
+    n2 = float(n * n)
+    per_app = 2 * n2 + 4 * 8 * n2 + 3 * 2 * n2 + 4 * n2 + 4 * n2
+    per_iter = 4 * n2 + 16 * n2
+    per_sweep = 16 * n2
+    return apps * per_app + iters * per_iter + sweeps * per_sweep
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "cg_onchip_128x32_fastpoisson_c3_counters.md")
@@ -185,6 +200,36 @@ def example1_variant(dev, N=20000, M=8, chain=200, K=64, sigma=0.1):
         out["example1_%s_stages" % name] = len(r["history"])
         if name != "smc_gm":
             out["example1_%s_moves_per_s" % name] = N * chain * len(r["history"]) / dt
+    return out
+
+
+def runs_variant(dev):
+    """Whole SMC-pCN-GM runs to temperature 1 of the 1D workload (64 intervals, N = 256, plain pCN, 10
+    moves per stage, FP64) and of the 64^2 workload (N = 1024, M = 4, 20 moves per stage) in FP64 and in
+    FP32 with refinement: wall time of each run after one warm-up run, and the moves per second."""
+    import torch
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCSampler
+    out = {}
+    for name, precs in (("c1", (("fp64", smc.SMC_FP64),)),
+                        ("c2", (("fp64", smc.SMC_FP64), ("fp32_refine", smc.SMC_FP32_REFINE)))):
+        d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_%s.json" % name)))
+        N, M, nm = int(d["N"]), int(d["M"]), int(d["n_moves"])
+        p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+        for tag, prec in precs:
+            make = lambda: SMCSampler(p, N, M, nm, ess_frac=d["ess_frac"], beta0=d["beta0"], prec=prec, seed=0,
+                                      device=dev)
+            make().run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = make().run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            stages = len(r["history"])
+            out["%s_%s_run_s" % (name, tag)] = dt
+            out["%s_%s_stages" % (name, tag)] = stages
+            out["%s_%s_moves_per_s" % (name, tag)] = N * nm * stages / dt
+        p.close()
     return out
 
 
@@ -392,6 +437,7 @@ def main():
         variants.update(smc_gm_variant(dev))
         variants.update(example1_variant(dev))
         variants.update(mixed_variant(dev))
+        variants.update(runs_variant(dev))
         # FP64 conjugate gradients with the same preconditioner, on the headline's protocol: the same
         # seed, stages, warm-up and moves per stage, so the ratio compares precisions alone
         t64, prof64, _ = stage_loop(smc.SMC_FP64, args.steps, args.warmup, args.moves)
@@ -439,6 +485,9 @@ def main():
     stream_model = N * (GRID ** 2) * (
         48.0 * prof32["iters"] / max(1, prof32["solves"]) + 20.0 * prof32["sweeps"] / max(1, prof32["solves"]) + 12.0)
     hbm_achieved = None if traffic is None else traffic / (kernel_ms * 1e-3)
+    solves32 = max(1, prof32["solves"])
+    lds_launch = N * lds_bytes_per_solve(prof32["iters"] / solves32, prof32["precond_apps"] / solves32,
+                                         prof32["sweeps"] / solves32)
     out = {
         "metric": "particle GM-pCN moves/sec (solve+Phi) at 128^2, N=4096; FP32+refine vs FP64",
         "value": value,
@@ -469,6 +518,9 @@ def main():
                      "kernel_ms_per_launch": kernel_ms,
                      "streaming_model_bytes_per_launch": stream_model,
                      "streaming_model_frac": stream_model / (kernel_ms * 1e-3) / HBM_PEAK,
+                     "lds": {"bytes_per_launch": lds_launch, "achieved": lds_launch / (kernel_ms * 1e-3) / 1e12,
+                             "peak": LDS_PEAK / 1e12, "unit": "TB/s",
+                             "frac": lds_launch / (kernel_ms * 1e-3) / LDS_PEAK},
                      "mfma": {"achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                               "frac": achieved / F16_MFMA_PEAK,
                               "counts": "8 n^3 FLOP of dense sine-transform products per preconditioner application"},

@@ -528,6 +528,14 @@ static hipError_t forward_levels(smc_problem_s* ps, int prec, int64_t N, const d
     return e;
 }
 
+// Whether the adjoint solve of grid `level` at precision `prec` forms dPhi/du itself: the on-chip
+// FP32 solvers with the fast-Poisson preconditioner on grids whose rows span whole waves (64, 128).
+static bool du_formed(const Problem& P, int level, int prec) {
+    const Level& L = P.lv[level];
+    return P.dim == 2 && prec == SMC_FP32_REFINE && P.precond == SMC_PRECOND_AUTO && L.dst_S &&
+           (L.n == 64 || L.n == 128);
+}
+
 static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, const double* xi, const Solve& o,
                           hipStream_t s) {
     const Problem& P = ps->P;
@@ -549,6 +557,12 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     a.fwd_given = o.w_given ? 1 : 0;
     a.lam = o.adjoint ? P.ws_lam : nullptr;
     a.stats = P.profiling ? P.stats : nullptr;
+    // the on-chip FP32 solvers form dPhi/du after the adjoint solve, into the scaling rows (free once
+    // the solve is done); the gradient then only contracts it (see du_formed)
+    if (o.adjoint && du_formed(P, level, prec)) {
+        a.du = P.ws_sd;
+        a.du_stride = P.x_stride;
+    }
     const bool rec = P.profiling && !ps->capturing;
     if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
     if (P.dim == 1)
@@ -564,12 +578,13 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
     return e;
 }
 
-// Gradient of the N particles' potentials after forward(..., adjoint = true).
-static hipError_t gradient(const Problem& P, int level, int64_t N, const double* w, int64_t w_stride,
+// Gradient of the N particles' potentials after forward(..., adjoint = true, prec).
+static hipError_t gradient(const Problem& P, int level, int prec, int64_t N, const double* w, int64_t w_stride,
                            const int32_t* iters, double* grad, hipStream_t s) {
     const Level& L = P.lv[level];
+    const bool du = du_formed(P, level, prec);
     return launch_gradsynth2d(P.ws_e, P.e_stride, w, w_stride, P.ws_lam, P.x_stride, iters, P.sqrt_lam, L.basis, L.n,
-                              P.kl, P.K, grad, N, s);
+                              P.kl, P.K, grad, N, du ? P.ws_sd : nullptr, P.x_stride, s);
 }
 
 extern "C" int smc_phi_batch(smc_problem p, int64_t N, const double* xi, const int32_t* level, int32_t prec,
@@ -646,7 +661,7 @@ extern "C" int smc_value_and_grad(smc_problem p, int64_t N, const double* xi, in
     }
     HIPCHK(forward(p, 0, prec, N, xi, o, s));
     const int n = P.lv[0].n;
-    HIPCHK(gradient(P, 0, N, w ? w : P.ws_x64, w ? (int64_t)n * n : P.x_stride, o.iters, grad, s));
+    HIPCHK(gradient(P, 0, prec, N, w ? w : P.ws_x64, w ? (int64_t)n * n : P.x_stride, o.iters, grad, s));
     return SMC_OK;
 }
 
@@ -968,7 +983,7 @@ extern "C" int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, 
         o.iters = P.ws_iters;
         o.adjoint = true;
         HIPCHK(forward(p, 0, prec, N, P.ws_v, o, s));
-        HIPCHK(gradient(P, 0, N, P.ws_x64, P.x_stride, P.ws_iters, P.ws_gnew, s));
+        HIPCHK(gradient(P, 0, prec, N, P.ws_x64, P.x_stride, P.ws_iters, P.ws_gnew, s));
         HIPCHK(launch_pcnl_accept(N, P.K, beta, tau, seed, c, P.ws_v, P.ws_gnew, P.ws_phinew, P.ws_iters, xi, grad,
                                   phi, n_acc, s));
     }

@@ -166,6 +166,8 @@ struct SolveArgs {
     int32_t* iters;      // [N] or null
     int32_t* flags;
     unsigned long long* stats;   // [4] iterations, sweeps, solves, preconditioner applications; or null
+    double* du;          // dPhi/du [N][du_stride] at every node, [j][i] on (n+1)^2, written after the
+    int64_t du_stride;   // adjoint solve by the on-chip solvers; null: not formed there
 };
 
 // Parameters of the moves of one call.  Either scalars for every particle, or per-group device
@@ -250,7 +252,8 @@ hipError_t launch_synth1d(const double* xi, int kl, const double* sqrt_lam, cons
                           int64_t out_stride, int64_t N, bool exp_half, hipStream_t s);
 hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w, int64_t w_stride,
                               const double* lam, int64_t lam_stride, const int32_t* iters, const double* sqrt_lam,
-                              const double* basis, int n, int kl, int K, double* grad, int64_t N, hipStream_t s);
+                              const double* basis, int n, int kl, int K, double* grad, int64_t N, const double* du,
+                              int64_t du_stride, hipStream_t s);
 hipError_t launch_pcnl_propose(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr,
                                const double* xi, const double* grad, double* v, hipStream_t s);
 hipError_t launch_pcnl_accept(int64_t N, int K, double beta, double tau, uint64_t seed, uint64_t ctr, const double* v,

@@ -466,6 +466,90 @@ __device__ __noinline__ void strip_update(double* xo_, const SD* sd_, const T* t
     }
 }
 
+// dPhi/du at the strip's nodes after the forward solution w and the adjoint solution lam are final
+// (App. B's gradient of the discrete potential, the derivative of the face coefficient a_PQ = e_P e_Q
+// by u_P being a_PQ / 2):
+//   du[P] = -(n^2 / 2) e_P sum_{Q nbr P} e_Q (lam_P - lam_Q)(w_P - w_Q),   w = lam = 0 on the boundary,
+// at every node of the (n+1)^2 grid, [j][i]: the thread's nodes are x-node i = c + 1, y-nodes
+// j = g0 + 1 .. g0 + R (i = n and j = n are boundary nodes); column 0 is done by the threads of c = 0
+// and row 0 by the strips at g0 = 0 (a boundary node's only interior neighbour is beside it).  w and
+// lam are in the interior layout [g][c] (index n - 1 holds 0); east and west values come from the
+// adjacent lanes, the wave edges load theirs (vector loads: lam is written by this launch).
+template <int NN, int R>
+__device__ __noinline__ void strip_dphi(const double* __restrict__ e_, const double* __restrict__ w_,
+                                        const double* __restrict__ l_, double* __restrict__ du_, int c, int g0) {
+    static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
+    constexpr int NP1 = NN + 1;
+    const double scale = -0.5 * (double)NN * (double)NN;
+    gcdp e = (gcdp)e_;
+    gcdp w = (gcdp)w_;
+    gcdp l = (gcdp)l_;
+    gdp du = (gdp)du_;
+    const int i = c + 1;
+    const int lane = threadIdx.x & 63;
+    const int c0 = __builtin_amdgcn_readfirstlane(c - lane);
+    const int ieE = min(c0 + 65, NN), ieW = c0;                     // e columns beyond the wave's edges
+    const int cxE = min(c0 + 64, NN - 1), cxW = max(c0 - 1, 0);     // interior columns beyond them
+    const bool xEok = c0 + 64 < NN - 1, xWok = c0 > 0;
+    const bool colin = c < NN - 1;
+    auto wl = [&](gcdp v, int g) -> double {   // interior value at (g, c), 0 outside the interior
+        const double x = v[min(max(g, 0), NN - 1) * NN + c];
+        return (g >= 0 && g < NN - 1 && colin) ? x : 0.0;
+    };
+    double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
+    double wS = wl(w, g0 - 1), wC = wl(w, g0), lS = wl(l, g0 - 1), lC = wl(l, g0);
+    constexpr int B = R < 8 ? R : 8;
+    static_assert(R % B == 0, "strip blocking");
+#pragma unroll 1
+    for (int r0 = 0; r0 < R; r0 += B) {
+        double eN[B], wN[B], lN[B], eEe[B], eWe[B], wEe[B], wWe[B], lEe[B], lWe[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int g = g0 + r0 + k, j = g + 1;
+            eN[k] = e[min(j + 1, NN) * NP1 + i];
+            wN[k] = wl(w, g + 1);
+            lN[k] = wl(l, g + 1);
+            eEe[k] = e[j * NP1 + ieE];
+            eWe[k] = e[j * NP1 + ieW];
+            const int gc = min(g, NN - 1);
+            wEe[k] = w[gc * NN + cxE];
+            wWe[k] = w[gc * NN + cxW];
+            lEe[k] = l[gc * NN + cxE];
+            lWe[k] = l[gc * NN + cxW];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int g = g0 + r0 + k, j = g + 1;
+            const bool rowin = g < NN - 1;
+            const double eE = from_next_lane(eC, eEe[k]);
+            const double eW = from_prev_lane(eC, eWe[k]);
+            const double wE_ = from_next_lane(wC, (xEok && rowin) ? wEe[k] : 0.0);
+            const double wW_ = from_prev_lane(wC, (xWok && rowin) ? wWe[k] : 0.0);
+            const double lE_ = from_next_lane(lC, (xEok && rowin) ? lEe[k] : 0.0);
+            const double lW_ = from_prev_lane(lC, (xWok && rowin) ? lWe[k] : 0.0);
+            const double wE = (c + 1 < NN - 1) ? wE_ : 0.0, lE = (c + 1 < NN - 1) ? lE_ : 0.0;
+            const double wW = (c > 0) ? wW_ : 0.0, lW = (c > 0) ? lW_ : 0.0;
+            double acc = 0.0;
+            acc += eW * (lC - lW) * (wC - wW);
+            acc += eE * (lC - lE) * (wC - wE);
+            acc += eS * (lC - lS) * (wC - wS);
+            acc += eN[k] * (lC - lN[k]) * (wC - wN[k]);
+            du[j * NP1 + i] = scale * eC * acc;
+            if (c == 0) du[j * NP1] = scale * eW * eC * lC * wC;      // node (0, j): its neighbour is (1, j)
+            if (g == 0) {
+                du[i] = scale * eS * eC * lC * wC;                     // node (i, 0): its neighbour is (i, 1)
+                if (c == 0) du[0] = 0.0;                               // corner: boundary neighbours only
+            }
+            eS = eC;
+            eC = eN[k];
+            wS = wC;
+            wC = wN[k];
+            lS = lC;
+            lC = lN[k];
+        }
+    }
+}
+
 // D^{-1/2} into the workspace and t = sqrt(e_P / sum e_Q) into the strip's LDS slots (SE as for
 // strip_residual).
 template <typename T, int NN, int R, typename SD, bool SE = true>
@@ -809,6 +893,9 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
         }
         ++solves;
         if (pass == 0) observe(ok);
+    }
+    if constexpr (ADJ && NN >= 64) {   // dPhi/du from the final w and lam (the barrier closing the last sweep made them whole)
+        if (a.du && ok) strip_dphi<NN, R>(e, x64, a.lam + row * a.lam_stride, a.du + row * a.du_stride, c, b * R);
     }
 
     // ---- bookkeeping

@@ -58,7 +58,8 @@ __global__ __launch_bounds__(256) void synth1d_kernel(const double* __restrict__
 //   dU[P] = dPhi/du_P = -(1/2) sum_{Q nbr P} a_PQ (lam_P - lam_Q)(w_P - w_Q) / h^2,  a_PQ = e_P e_Q,
 // and the transpose of the separable synthesis gives
 //   g_kl = sqrt(lambda_kl) sum_j sum_i B[i][k] dU[j][i] B[j][l].
-// dU is formed 32 grid rows at a time in LDS and contracted on the FP64 matrix cores:
+// dU is formed 32 grid rows at a time in LDS (or read from `du`, where the on-chip adjoint solve
+// formed it already) and contracted on the FP64 matrix cores:
 //   T[j][k] = sum_i dU[j][i] B[i][k] for the block's rows j, then H[k][l] += sum_j T[j][k] B[j][l].
 // A particle whose solves did not converge (iters < 0) gets a NaN gradient.
 __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restrict__ e, int64_t e_stride,
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
                                                           const int32_t* __restrict__ iters,
                                                           const double* __restrict__ sqrt_lam,
                                                           const double* __restrict__ basis, int n, int kl, int K,
-                                                          double* __restrict__ grad) {
+                                                          double* __restrict__ grad, const double* __restrict__ du,
+                                                          int64_t du_stride) {
     extern __shared__ double smem[];
     const int np1 = n + 1;
     const int ipad = (np1 + 3) & ~3;
@@ -93,7 +95,9 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
         for (int t = threadIdx.x; t < 32 * ipad; t += 256) {
             const int r = t / ipad, i = t % ipad, j = jb + r;
             double v = 0.0;
-            if (j <= n && i <= n) {
+            if (j <= n && i <= n && du) {
+                v = du[p * du_stride + j * np1 + i];   // formed by the adjoint solve
+            } else if (j <= n && i <= n) {
                 const double wP = at(wp, j, i), lP = at(lp, j, i);
                 double acc = 0.0;
                 if (i > 0) acc += ep[j * np1 + i - 1] * (lP - at(lp, j, i - 1)) * (wP - at(wp, j, i - 1));
@@ -136,12 +140,13 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
 
 hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w, int64_t w_stride,
                               const double* lam, int64_t lam_stride, const int32_t* iters, const double* sqrt_lam,
-                              const double* basis, int n, int kl, int K, double* grad, int64_t N, hipStream_t s) {
+                              const double* basis, int n, int kl, int K, double* grad, int64_t N, const double* du,
+                              int64_t du_stride, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     const int ipad = (n + 1 + 3) & ~3;
     const size_t lds = sizeof(double) * (32 * (size_t)(ipad + 1) + 32 * (size_t)(KLP + 1));
     gradsynth2d_kernel<<<dim3((unsigned)N), dim3(256), lds, s>>>(e, e_stride, w, w_stride, lam, lam_stride, iters,
-                                                                 sqrt_lam, basis, n, kl, K, grad);
+                                                                 sqrt_lam, basis, n, kl, K, grad, du, du_stride);
     return hipGetLastError();
 }
 
