@@ -571,6 +571,8 @@ static hipError_t forward(smc_problem_s* ps, int level, int prec, int64_t N, con
         e = launch_solve2d_dst(L.n, L.rows, N, a, L.dst_S, L.dst_lam, s);
     else if (prec == SMC_FP64 && P.precond == SMC_PRECOND_AUTO && L.dst_S && (L.n == 128 || L.n == 256))
         e = launch_solve2d_dst64(L.n, N, a, L.dst_S, L.dst_lam, s);
+    else if (prec == SMC_FP64 && P.precond == SMC_PRECOND_AUTO && L.dst_S && (L.n == 32 || L.n == 64))
+        e = launch_solve2d_dst64_onchip(L.n, N, a, L.dst_S, L.dst_lam, s);
     else
         e = launch_solve2d(L.n, prec, N, a, s);
     if (e != hipSuccess) return e;

@@ -267,6 +267,8 @@ hipError_t launch_solve2d_dst(int n, int rows, int64_t N, const SolveArgs& a, co
                               hipStream_t s);
 hipError_t launch_solve2d_dst64(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam,
                                 hipStream_t s);
+hipError_t launch_solve2d_dst64_onchip(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam,
+                                       hipStream_t s);
 hipError_t launch_dst_apply(int n, int64_t N, const float* r, float* z, const void* S, const float* lam,
                             hipStream_t s);
 

@@ -1773,6 +1773,18 @@ hipError_t launch_solve2d(int n, int prec, int64_t N, const SolveArgs& a, hipStr
     }
 }
 
+// FP64 conjugate gradients on chip with the fast-Poisson preconditioner (FP16 transforms, a
+// perturbation of the preconditioner only), to 0.1 tol64 in one sweep: 32^2 and 64^2.
+hipError_t launch_solve2d_dst64_onchip(int n, int64_t N, const SolveArgs& a, const void* S, const float* lam,
+                                       hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    SolveArgs b = a;
+    b.tol_inner = 0.1 * a.tol64;
+    if (n == 32) return run_onchip<double, 32, 4, true>(N, b, S, lam, s);
+    if (n == 64) return run_onchip<double, 64, 8, true>(N, b, S, lam, s);
+    return hipErrorInvalidValue;
+}
+
 // FP64 conjugate gradients with the fast-Poisson preconditioner (FP16 transforms, a perturbation of
 // the preconditioner only) on the 128 and 256 grids, vectors in global memory, to 0.1 tol64 in one
 // sweep.
