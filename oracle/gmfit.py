@@ -14,19 +14,23 @@ the oracle's own tests.
 Two seedings:
   fit          k-means++ with NumPy's generator (the oracle's own SMC loop);
   fit_philox   k-means++ with draws from the Philox layout of `philox`, which the GPU
-               fit reproduces exactly:
+               fit follows:
     * the uniform of centre m is the 53-bit integer u_m = (w0 >> 5) 2^26 + (w1 >> 6) of
       block KMPP_BLOCK, particle word m, at the call's counter;
     * centre 0 is row floor(u_0 N / 2^53);
     * for m >= 1, d2_n is the smallest squared distance of row n to the centres so far,
-      each squared distance summed over the K_r coordinates (zero-padded to 64) in the
-      pairwise order of `tree_sum64`;
+      each squared distance the exactly rounded sum (math.fsum) of the K_r squared
+      coordinate differences;
     * with D = max_n d2_n = f 2^e (f in [1/2, 1)), q_n = floor(d2_n 2^(40 - e)) are
       exact integers below 2^40; C_n = q_0 + ... + q_n, Q = C_{N-1};
-    * centre m is row min{n : C_n > floor(u_m Q / 2^53)} (probability q_n / Q), or row
-      floor(u_m N / 2^53) when Q = 0 (every row is a centre already).
-    Integer sums make the choice independent of summation order; the only floating
-    point that decides it is d2_n, whose order `tree_sum64` fixes.
+    * centre m is row min{n : C_n > t}, t = floor(u_m Q / 2^53) (probability q_n / Q), or
+      row floor(u_m N / 2^53) when Q = 0 (every row is a centre already).
+    Integer sums make the choice independent of summation order; the floating point that
+    decides it is d2_n.  Any other summation order of the K_r <= 64 non-negative terms
+    (the device adds them pairwise) is within 7 eps of d2_n, which moves each q_n by at
+    most 1, each C_n and Q by at most N and t by at most N + 1: a choice whose margin
+    min(t - C_{n-1}, C_n - 1 - t) exceeds 2 N + 2, with D not within 7 eps of a power of
+    two, is the same for every order (`kmeanspp_philox(..., margins=True)` reports both).
 """
 import math
 
@@ -93,17 +97,10 @@ def fit(X, M, seed=0, iters=50, var_floor=1e-3):
 
 # ---------------------------------------------------------------- Philox-seeded variant
 
-def tree_sum64(v):
-    """Sum over the last axis (length <= 64, zero-padded to 64) in pairwise halving order:
-    s <- s[:w] + s[w:2w] for w = 32, 16, ..., 1."""
+def exact_row_sums(v):
+    """Each row's sum, exactly rounded (math.fsum)."""
     v = np.asarray(v, dtype=np.float64)
-    s = np.zeros(v.shape[:-1] + (64,))
-    s[..., :v.shape[-1]] = v
-    w = 32
-    while w >= 1:
-        s = s[..., :w] + s[..., w:2 * w]
-        w //= 2
-    return s[..., 0]
+    return np.array([math.fsum(row) for row in v.reshape(-1, v.shape[-1])]).reshape(v.shape[:-1])
 
 
 def kmpp_u53(seed, ctr, m):
@@ -113,31 +110,38 @@ def kmpp_u53(seed, ctr, m):
     return (int(w[0]) >> 5) * (1 << 26) + (int(w[1]) >> 6)
 
 
-def kmeanspp_philox(X, M, seed, ctr):
-    """Row indices of the M seeded centres (see the module docstring)."""
+def kmeanspp_philox(X, M, seed, ctr, margins=False):
+    """Row indices of the M seeded centres (see the module docstring).  With margins=True also
+    returns, for every centre drawn with Q > 0, (margin, bound, power_of_two_clear): its
+    distance in integer units from the nearest choice boundary, 2 N + 2, and whether D is more
+    than 7 eps from a power of two."""
     X = np.asarray(X, dtype=np.float64)
     N = X.shape[0]
     idx = [(kmpp_u53(seed, ctr, 0) * N) >> 53]
+    info = []
     d2 = np.full(N, np.inf)
     for m in range(1, M):
         r = X - X[idx[-1]]
-        d2 = np.minimum(d2, tree_sum64(r * r))
+        d2 = np.minimum(d2, exact_row_sums(r * r))
         u = kmpp_u53(seed, ctr, m)
         dmax = float(d2.max())
         if dmax == 0.0:
             idx.append((u * N) >> 53)
             continue
-        e = math.frexp(dmax)[1]
+        f, e = math.frexp(dmax)
         q = [math.floor(math.ldexp(float(v), QBITS - e)) for v in d2]
         Q = sum(q)
         t = (u * Q) >> 53
         c = 0
         for n, qn in enumerate(q):
+            prev = c
             c += qn
             if c > t:
                 idx.append(n)
+                eps7 = 7 * np.finfo(float).eps
+                info.append((min(t - prev, c - 1 - t), 2 * N + 2, 0.5 + eps7 < f < 1.0 - eps7))
                 break
-    return idx
+    return (idx, info) if margins else idx
 
 
 def fit_philox(X, M, seed, ctr, iters=50, var_floor=1e-3):

@@ -1,8 +1,11 @@
 """SMC-GM on the GPU against the oracle: mixture fit, mixture draw and the whole Alg. 3 loop.
 
   * smc_gm_fit: the seeded centres are integer decisions and must match the oracle's
-    (`gmfit.kmeanspp_philox`) exactly; the EM parameters from the same start match to 1e-9
-    relative (both FP64; only the order of the partial sums differs);
+    (`gmfit.kmeanspp_philox`) exactly on tie-free inputs: the oracle sums each squared distance
+    exactly rounded and the device pairwise, and every test input is checked (by the oracle) to
+    keep each choice more than the bound 2 N + 2 integer units from a tie, beyond what the two
+    orders can differ by; the EM parameters from the same start match to 1e-9 relative (both
+    FP64; only the order of the partial sums differs);
   * smc_gm_draw: the draws match the oracle's (`moves.gm_draw`) to 1e-12 and their potentials
     to 1e-9 (FP64 path) or 1e-4 (FP32 + refinement), as the move parity tests;
   * SMCGMSampler: a whole run on the mirrored 1D problem against the oracle's run of Alg. 3
@@ -96,7 +99,8 @@ def test_gm_fit_against_oracle(name, N, M, iters, seed, dup):
     ctr = 77 + seed
     c, logw, mean, var = gpu_fit(p, op, xi, M, iters, 5 + seed, ctr)
     X = xi[:, op.active()]
-    rc = gmfit.kmeanspp_philox(X, M, 5 + seed, ctr)
+    rc, info = gmfit.kmeanspp_philox(X, M, 5 + seed, ctr, margins=True)
+    assert all(mg > bound and clear for mg, bound, clear in info)   # tie-free: every summation order agrees
     assert c.tolist() == rc
     rlogw, rmean, rvar = gmfit.em(X, *gmfit.start(X, rc), iters)
     assert np.abs(logw - rlogw).max() <= 1e-9 * max(1.0, np.abs(rlogw).max())
@@ -116,7 +120,8 @@ def test_gm_fit_repeat_and_smaller():
         xi = cloud(op, N, seed)
         c, logw, mean, var = gpu_fit(p, op, xi, M, 15, seed, 3)
         X = xi[:, op.active()]
-        rc = gmfit.kmeanspp_philox(X, M, seed, 3)
+        rc, info = gmfit.kmeanspp_philox(X, M, seed, 3, margins=True)
+        assert all(mg > bound and clear for mg, bound, clear in info)
         assert c.tolist() == rc
         rlogw, rmean, rvar = gmfit.em(X, *gmfit.start(X, rc), 15)
         assert np.abs(mean - rmean).max() <= 1e-9 * max(1.0, np.abs(rmean).max())

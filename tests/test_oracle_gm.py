@@ -19,29 +19,46 @@ from oracle.moves import GM, gm_draw, pcn_gm
 
 # ------------------------------------------------------------------ seeding
 
-def test_tree_sum_is_the_xor_butterfly_of_a_64_lane_wave():
-    """Lane 0 of v += v[lane ^ off] (off = 32 .. 1) is the pairwise halving sum, bit for bit."""
-    rng = np.random.default_rng(0)
-    for kr in (64, 37, 1):
-        v = rng.standard_normal(kr) * 10.0 ** rng.integers(-8, 8, kr)
-        lanes = np.zeros(64)
-        lanes[:kr] = v
-        off = 32
-        while off:
-            lanes = lanes + lanes[np.arange(64) ^ off]
-            off //= 2
-        assert np.all(lanes == lanes[0])
-        assert gmfit.tree_sum64(v) == lanes[0]
-
-
-def test_tree_sum_error_bound():
-    """Pairwise summation over 64 terms: |error| <= 6 eps sum|v| (against math.fsum)."""
+def test_squared_distances_are_exactly_rounded():
+    """The seeding's distances are the exactly rounded sums of the squared differences: against
+    rational arithmetic, and equal to the exact integer sum where that is representable."""
+    from fractions import Fraction
     rng = np.random.default_rng(1)
-    for _ in range(50):
-        v = rng.standard_normal(64) ** 2 * 10.0 ** rng.integers(-3, 3, 64)
-        assert abs(gmfit.tree_sum64(v) - math.fsum(v)) <= 6 * np.finfo(float).eps * np.abs(v).sum()
-    ints = rng.integers(0, 1000, 64).astype(float)
-    assert gmfit.tree_sum64(ints) == ints.sum()
+    for kr in (64, 37, 1):
+        v = rng.standard_normal((20, kr)) ** 2 * 10.0 ** rng.integers(-8, 8, (20, kr))
+        got = gmfit.exact_row_sums(v)
+        for row, g in zip(v, got):
+            exact = sum(Fraction(float(x)) for x in row)
+            assert g == float(exact)     # float(Fraction) rounds to nearest
+    ints = rng.integers(0, 1000, (3, 64)).astype(float)
+    assert np.array_equal(gmfit.exact_row_sums(ints), ints.sum(axis=1))
+
+
+def test_choice_margin_covers_any_summation_order():
+    """Moving each integer weight by at most 1 (what another summation order of the distances can
+    do) never changes a choice whose reported margin exceeds the bound: brute force over random
+    perturbations of the same weights."""
+    X = inputs.particles(300, 16, 21)
+    rng = np.random.default_rng(2)
+    for ctr in range(6):
+        idx, info = gmfit.kmeanspp_philox(X, 5, seed=4, ctr=ctr, margins=True)
+        assert len(info) == 4 and all(clear for _, _, clear in info)
+        assert all(mg > bound for mg, bound, _ in info)
+    # the margin arithmetic itself: perturb q by +-1 and recompute the choice
+    q = rng.integers(0, 1 << 40, 300)
+    u = int(rng.integers(0, 1 << 53))
+    def choose(qq):
+        t = (u * int(sum(int(x) for x in qq))) >> 53
+        c = 0
+        for n, x in enumerate(qq):
+            c += int(x)
+            if c > t:
+                return n, t, c - int(x), c
+    n0, t, lo, hi = choose(q)
+    margin = min(t - lo, hi - 1 - t)
+    if margin > 2 * q.size + 2:
+        for _ in range(200):
+            assert choose(q + rng.integers(-1, 2, q.size))[0] == n0
 
 
 def test_kmeanspp_all_rows_when_m_equals_n():
