@@ -240,8 +240,8 @@ extern "C" int smc_problem_create(const smc_problem_desc* d, smc_problem* out) {
     ck(hipMalloc((void**)&P.ws_G, sizeof(double) * Nm * P.n_obs));
     ck(hipMalloc((void**)&P.ws_iters, sizeof(int32_t) * Nm));
     ck(hipMalloc((void**)&P.ws_list, sizeof(int32_t) * Nm));
-    ck(hipMalloc((void**)&P.ws_counters, 2 * sizeof(unsigned long long)));
-    ck(hipMemset(P.ws_counters, 0, 2 * sizeof(unsigned long long)));
+    ck(hipMalloc((void**)&P.ws_counters, N_COUNTERS * sizeof(unsigned long long)));
+    ck(hipMemset(P.ws_counters, 0, N_COUNTERS * sizeof(unsigned long long)));
     {
         const size_t pe = (size_t)MAX_M * (1 + 2 * MAX_KR);
         ck(hipMalloc((void**)&P.ws_fit_d2, sizeof(double) * Nm));
@@ -522,7 +522,13 @@ static hipError_t forward_levels(smc_problem_s* ps, int prec, int64_t N, const d
     const bool rec = P.profiling && !ps->capturing;
     if (rec && (e = record(ps->pool, s)) != hipSuccess) return e;
     const bool dst = P.precond == SMC_PRECOND_AUTO;
-    e = launch_solve_mixed(prec, dst, N, a, lt, o.level, P.ws_list, P.ws_counters, P.n_cu, s);
+    if (dst) {   // one launch per grid, each in its single-grid shape
+        int rows[MAX_LEVELS] = {};
+        for (int l = 0; l < P.n_levels; ++l) rows[l] = P.lv[l].rows;
+        e = launch_solve_levels(prec, N, a, lt, rows, P.ws_list, P.ws_counters, P.n_cu, s);
+    } else {
+        e = launch_solve_mixed(prec, dst, N, a, lt, o.level, P.ws_list, P.ws_counters, P.n_cu, s);
+    }
     if (e != hipSuccess) return e;
     if (rec) e = record(ps->pool, s);
     return e;

@@ -29,6 +29,7 @@
 // of the wave partials: every thread sees the same bits, and a particle's result does not depend
 // on the batch it is solved in.
 #include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 #include "move_body.hpp"
@@ -1439,8 +1440,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __
     __shared__ int order[MAX_LEVELS + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) {
-        counters[0] = 0;
-        counters[1] = 0;
+        for (int k = 0; k < COUNTER_SEG; ++k) counters[k] = 0;
         bool used[MAX_LEVELS] = {};
         for (int r = 0; r < lt.n_levels; ++r) {
             int best = -1;
@@ -1456,6 +1456,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __
     bool bad = false;
     for (int rank = 0; rank <= lt.n_levels; ++rank) {
         const int target = order[rank];
+        const int64_t seg0 = base;
         for (int64_t c0 = 0; c0 < N; c0 += 1024) {
             const int64_t p = c0 + tid;
             bool f = false;
@@ -1478,7 +1479,14 @@ __global__ __launch_bounds__(1024) void plan_kernel(int64_t N, const int32_t* __
             base += tot;
             __syncthreads();
         }
+        if (tid == 0) {   // this grid's segment of the list (the last one: no grid)
+            const int sl = target >= 0 ? target : MAX_LEVELS;
+            counters[COUNTER_SEG + 2 * sl] = (unsigned long long)seg0;
+            counters[COUNTER_SEG + 2 * sl + 1] = (unsigned long long)(base - seg0);
+        }
     }
+    if (tid == 0)   // grids absent from the table hold no particles
+        for (int l = lt.n_levels; l < MAX_LEVELS; ++l) counters[COUNTER_SEG + 2 * l + 1] = 0;
     if (__syncthreads_or(bad) && tid == 0 && flags) atomicOr(flags, SMC_FLAG_BADLEVEL);
 }
 
@@ -1678,6 +1686,126 @@ hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a,
         else
             solve_mixed_kernel<SMC_FP64, false><<<dim3(g), dim3(1024), 0, s>>>(b, lt, level, list, N, counters);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ one launch per grid of a level map
+// plan_kernel leaves grid l's particles in list[start .. start + count) (start and count at
+// COUNTER_SEG + 2 l); each grid is solved by a persistent launch in the workgroup shape of its
+// single-grid launch (the same body, so the same bits), taking items from its own counter pair; the
+// last workgroup to leave zeroes the pair for the next launch or graph replay.
+template <typename F>
+__device__ __forceinline__ void list_loop(unsigned long long* counters, int lvl, const int32_t* __restrict__ list,
+                                          unsigned long long* item_s, F&& body) {
+    const int64_t start = __builtin_amdgcn_readfirstlane((int)counters[COUNTER_SEG + 2 * lvl]);
+    const int64_t count = __builtin_amdgcn_readfirstlane((int)counters[COUNTER_SEG + 2 * lvl + 1]);
+    unsigned long long* ctr = counters + COUNTER_LIST + 2 * lvl;
+    for (;;) {
+        if (threadIdx.x == 0) *item_s = atomicAdd(&ctr[0], 1ull);
+        __syncthreads();
+        // wave-uniform item: the loop exit must be a uniform branch (see solve_mixed_kernel)
+        const int64_t item =
+            __builtin_amdgcn_readfirstlane((int)(*item_s < (unsigned long long)count ? *item_s : count));
+        __syncthreads();
+        if (item >= count) break;
+        const int64_t p = __builtin_amdgcn_readfirstlane(list[start + item]);
+        body(p);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long done = atomicAdd(&ctr[1], 1ull);
+        if (done == (unsigned long long)gridDim.x - 1ull) {   // every workgroup has stopped fetching
+            ctr[0] = 0;
+            ctr[1] = 0;
+        }
+    }
+}
+
+template <typename T, int NN, int R>
+__global__ __launch_bounds__(NN * NN / R) void solve_list_onchip(SolveArgs a, const int32_t* __restrict__ list,
+                                                                 unsigned long long* counters, int lvl,
+                                                                 const int32_t* __restrict__ obs,
+                                                                 const _Float16* __restrict__ Stab,
+                                                                 const float* __restrict__ lamtab) {
+    __shared__ __align__(16) unsigned char smem[onchip_smem<T, NN, R, true>()];
+    __shared__ SolveShared sh;
+    __shared__ unsigned long long item_s;
+    list_loop(counters, lvl, list, &item_s,
+              [&](int64_t p) { cg_onchip_body<T, NN, R, true, false>(a, p, obs, smem, sh, Stab, lamtab); });
+}
+
+template <typename T, int NN>
+__global__ __launch_bounds__(1024) void solve_list_global(SolveArgs a, const int32_t* __restrict__ list,
+                                                          unsigned long long* counters, int lvl,
+                                                          const int32_t* __restrict__ obs,
+                                                          const _Float16* __restrict__ Stab,
+                                                          const float* __restrict__ lamtab) {
+    __shared__ SolveShared sh;
+    __shared__ unsigned long long item_s;
+    list_loop(counters, lvl, list, &item_s, [&](int64_t p) {
+        cg_global_body<T, false, true, NN>(a, p, NN, obs, sh, reinterpret_cast<_Float16*>(g_mixed_smem), Stab, lamtab);
+    });
+}
+
+// The particles with no grid (parked or out of range): the outputs of a rejected proposal.
+__global__ __launch_bounds__(256) void reject_list_kernel(SolveArgs a, const int32_t* __restrict__ list,
+                                                          const unsigned long long* counters) {
+    const int64_t start = (int64_t)counters[COUNTER_SEG + 2 * MAX_LEVELS];
+    const int64_t count = (int64_t)counters[COUNTER_SEG + 2 * MAX_LEVELS + 1];
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const int64_t p = list[start + k];
+    if (a.G)
+        for (int o = 0; o < a.n_obs; ++o) a.G[p * a.n_obs + o] = NAN;
+    if (a.phi) a.phi[p] = INFINITY;
+    if (a.iters) a.iters[p] = -1;
+}
+
+hipError_t launch_solve_levels(int prec, int64_t N, const SolveArgs& a, const LevelTable& lt, const int* rows,
+                               const int32_t* list, unsigned long long* counters, int n_cu, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    int order[MAX_LEVELS];   // finest grid first, as the list is
+    for (int l = 0; l < lt.n_levels; ++l) order[l] = l;
+    for (int i = 0; i < lt.n_levels; ++i)
+        for (int j = i + 1; j < lt.n_levels; ++j)
+            if (lt.n[order[j]] > lt.n[order[i]]) std::swap(order[i], order[j]);
+    SolveArgs b = a;
+    if (prec == SMC_FP64) b.tol_inner = 0.1 * a.tol64;   // FP64 CG to 0.1 tol64 in one sweep, as single-grid
+    const dim3 g1((unsigned)n_cu), g4((unsigned)(4 * n_cu));
+    for (int k = 0; k < lt.n_levels; ++k) {
+        const int l = order[k], n = lt.n[l];
+        const _Float16* S = reinterpret_cast<const _Float16*>(lt.S[l]);
+        const float* lam = lt.lam[l];
+        const int32_t* obs = lt.obs[l];
+        if (prec == SMC_FP32_REFINE) {
+            if (n == 256)
+                solve_list_global<float, 256><<<g1, dim3(1024), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 128 && rows[l] == 16)
+                solve_list_onchip<float, 128, 16><<<g1, dim3(1024), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 128)
+                solve_list_onchip<float, 128, 32><<<g1, dim3(512), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 64 && rows[l] == 4)
+                solve_list_onchip<float, 64, 4><<<g4, dim3(1024), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 64 && rows[l] == 16)
+                solve_list_onchip<float, 64, 16><<<g4, dim3(256), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 64)
+                solve_list_onchip<float, 64, 8><<<g4, dim3(512), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else
+                return hipErrorInvalidValue;
+        } else {
+            if (n == 256)
+                solve_list_global<double, 256><<<g1, dim3(1024), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 128)
+                solve_list_global<double, 128><<<g1, dim3(1024), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else if (n == 64)
+                solve_list_onchip<double, 64, 8><<<g4, dim3(512), 0, s>>>(b, list, counters, l, obs, S, lam);
+            else
+                return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    reject_list_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(b, list, counters);
     return hipGetLastError();
 }
 

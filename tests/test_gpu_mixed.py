@@ -55,9 +55,9 @@ LEVELS = np.array([2, 1, 0, 0, 1, 0, 1, 0], dtype=np.int32)
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32_refine"])
 def test_forward_levels(prec_name):
-    """One launch over 64^2, 128^2 and 256^2 particles; each row equals the oracle on its grid,
-    and the 128^2 and 256^2 rows equal, bit for bit, the single-grid launch with the same solver
-    body and tile shape."""
+    """One call over 64^2, 128^2 and 256^2 particles (one launch per grid, each in its single-grid
+    shape); each row equals the oracle on its grid, and every row equals, bit for bit, the
+    single-grid launch."""
     from paper_2503_16028_amd import smc
     banner("forward levels", prec_name)
     d, op = load("c5")
@@ -77,12 +77,10 @@ def test_forward_levels(prec_name):
         n = GRIDS[LEVELS[k]]
         ref = observe(op, solve(op, synthesize(op, xi[k], n), n), n)
         assert np.abs(got[k] - ref).max() <= tol * np.abs(ref).max(), (k, n)
-    for lv in (1, 2):
+    for lv in (0, 1, 2):
         rows = np.nonzero(LEVELS == lv)[0]
         q = smc.Problem(d, len(rows), grids=[GRIDS[lv]], tol64=p_tol(prec_name), tol_inner=1e-5,
                         max_iter=(60 if prec_name == "fp64" else 80) * 256, max_sweeps=6 if prec_name == "fp64" else 8)
-        if prec_name == "fp32_refine" and GRIDS[lv] == 128:
-            smc.smc_set_tile(q, 0, 16)       # the shape the mixed launch runs (1024 threads)
         G1 = torch.empty(len(rows), op.n_obs, dtype=torch.float64, device=DEV)
         smc.smc_forward_batch(q, len(rows), t(xi[rows]), None, prec, G1)
         torch.cuda.synchronize()
