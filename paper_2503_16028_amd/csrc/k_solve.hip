@@ -295,6 +295,7 @@ __device__ __forceinline__ double strip_rhs(int flat, bool sources, double f, co
     return s;
 }
 
+
 // A pointer every lane holds, made visibly wave-uniform (its loads can then go through the
 // scalar unit; used only for data the kernel does not write).
 __device__ __forceinline__ const double* wave_uniform(const double* p) {
@@ -327,7 +328,9 @@ __device__ __forceinline__ double from_prev_lane(double v, double edge) {
 // the vector registers to the rows' loads).  The scalar cache does not see vector stores, so SE is
 // only for a field no store of the same launch has written (the synthesis ran in an earlier one);
 // a launch that synthesises the field itself loads the edges as vectors.
-template <typename T, int NN, int R, bool SRC, typename SD, bool SE = true>
+// MANY: a strip holding more sources than the list keeps sums over every source at each row (a
+// separate instantiation, so that the common one carries no such loop per unrolled row).
+template <typename T, int NN, int R, bool SRC, typename SD, bool SE = true, bool MANY = false>
 __device__ __noinline__ double strip_residual(const double* __restrict__ e_, const double* __restrict__ xo_,
                                               const SD* __restrict__ sd_, T* __restrict__ tb_, int c, int g0,
                                               bool zero_x, double f, const double* __restrict__ src_w,
@@ -367,12 +370,17 @@ __device__ __noinline__ double strip_residual(const double* __restrict__ e_, con
                 ++ns;
             }
         }
+        if constexpr (!MANY) {   // the whole wave together: the pass exchanges values between lanes
+            if (__any(ns > SMAX))
+                return strip_residual<T, NN, R, true, SD, SE, true>(e_, xo_, sd_, tb_, c, g0, zero_x, f, src_w, src_at,
+                                                                    n_obs);
+        }
     }
     auto rhs_at = [&](int r) -> double {
         if constexpr (!SRC) {
             return f;
         } else {
-            if (ns > SMAX) return strip_rhs((g0 + r) * NN + c, true, f, g_src_w, g_src_at, n_obs);
+            if constexpr (MANY) return strip_rhs((g0 + r) * NN + c, true, f, g_src_w, g_src_at, n_obs);
             double v = 0.0;
 #pragma unroll
             for (int q = 0; q < SMAX; ++q) v += (srow[q] == r) ? sw[q] : 0.0;
@@ -475,8 +483,11 @@ __device__ __noinline__ void strip_update(double* xo_, const SD* sd_, const T* t
 // j = g0 + 1 .. g0 + R (i = n and j = n are boundary nodes); column 0 is done by the threads of c = 0
 // and row 0 by the strips at g0 = 0 (a boundary node's only interior neighbour is beside it).  w and
 // lam are in the interior layout [g][c] (index n - 1 holds 0); east and west values come from the
-// adjacent lanes, the wave edges load theirs (vector loads: lam is written by this launch).
-template <int NN, int R>
+// adjacent lanes, the wave edges load theirs: e's through the scalar unit (no launch writes it while
+// it runs), lam's with vector loads (this launch wrote it), w's through the scalar unit when an
+// earlier launch wrote it (WS) and with vector loads otherwise.  The scalar edges leave the vector
+// registers to the strip's own loads, eight rows in flight without spilling.
+template <int NN, int R, bool WS>
 __device__ __noinline__ void strip_dphi(const double* __restrict__ e_, const double* __restrict__ w_,
                                         const double* __restrict__ l_, double* __restrict__ du_, int c, int g0) {
     static_assert(NN % 64 == 0, "a wave covers consecutive columns of one row");
@@ -486,6 +497,8 @@ __device__ __noinline__ void strip_dphi(const double* __restrict__ e_, const dou
     gcdp w = (gcdp)w_;
     gcdp l = (gcdp)l_;
     gdp du = (gdp)du_;
+    kcdp eu = (kcdp)wave_uniform(e_);
+    kcdp wu = (kcdp)wave_uniform(w_);
     const int i = c + 1;
     const int lane = threadIdx.x & 63;
     const int c0 = __builtin_amdgcn_readfirstlane(c - lane);
@@ -497,6 +510,7 @@ __device__ __noinline__ void strip_dphi(const double* __restrict__ e_, const dou
         const double x = v[min(max(g, 0), NN - 1) * NN + c];
         return (g >= 0 && g < NN - 1 && colin) ? x : 0.0;
     };
+    const int g0u = __builtin_amdgcn_readfirstlane(g0);
     double eS = e[g0 * NP1 + i], eC = e[(g0 + 1) * NP1 + i];
     double wS = wl(w, g0 - 1), wC = wl(w, g0), lS = wl(l, g0 - 1), lC = wl(l, g0);
     constexpr int B = R < 8 ? R : 8;
@@ -507,14 +521,14 @@ __device__ __noinline__ void strip_dphi(const double* __restrict__ e_, const dou
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int g = g0 + r0 + k, j = g + 1;
+            const int ju = g0u + r0 + k + 1, gcu = min(ju - 1, NN - 1), gc = min(g, NN - 1);
             eN[k] = e[min(j + 1, NN) * NP1 + i];
             wN[k] = wl(w, g + 1);
             lN[k] = wl(l, g + 1);
-            eEe[k] = e[j * NP1 + ieE];
-            eWe[k] = e[j * NP1 + ieW];
-            const int gc = min(g, NN - 1);
-            wEe[k] = w[gc * NN + cxE];
-            wWe[k] = w[gc * NN + cxW];
+            eEe[k] = eu[ju * NP1 + ieE];
+            eWe[k] = eu[ju * NP1 + ieW];
+            wEe[k] = WS ? wu[gcu * NN + cxE] : w[gc * NN + cxE];
+            wWe[k] = WS ? wu[gcu * NN + cxW] : w[gc * NN + cxW];
             lEe[k] = l[gc * NN + cxE];
             lWe[k] = l[gc * NN + cxW];
         }
@@ -896,7 +910,7 @@ __device__ __forceinline__ void cg_onchip_body(const SolveArgs& a, const int64_t
         if (pass == 0) observe(ok);
     }
     if constexpr (ADJ && NN >= 64) {   // dPhi/du from the final w and lam (the barrier closing the last sweep made them whole)
-        if (a.du && ok) strip_dphi<NN, R>(e, x64, a.lam + row * a.lam_stride, a.du + row * a.du_stride, c, b * R);
+        if (a.du && ok) strip_dphi<NN, R, AONLY>(e, x64, a.lam + row * a.lam_stride, a.du + row * a.du_stride, c, b * R);
     }
 
     // ---- bookkeeping

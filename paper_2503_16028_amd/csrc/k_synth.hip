@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
     const int lr = lane & 15, lk = lane >> 4;
     const int tj0 = (wave >> 1) * 16, tk0 = (wave & 1) * 16;   // this wave's T tile (block rows, k)
     const int hk0 = (wave & 1) * 16, hl0 = (wave >> 1) * 16;   // this wave's H tile (k, l)
-    d4 hacc = {0.0, 0.0, 0.0, 0.0};
+    d4 hacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int jb = 0; jb < np1; jb += 32) {
         for (int t = threadIdx.x; t < 32 * ipad; t += 256) {
             const int r = t / ipad, i = t % ipad, j = jb + r;
@@ -109,24 +109,34 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
             D[r * LDD + i] = v;
         }
         __syncthreads();
-        {   // T[r][k] = sum_i D[r][i] B[i][k]
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int i0 = 0; i0 < ipad; i0 += 4) {
-                const int ii = i0 + lk;
-                const double av = D[(tj0 + lr) * LDD + ii];
-                const double bv = (ii <= n) ? basis[ii * KLP + tk0 + lr] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        {   // T[r][k] = sum_i D[r][i] B[i][k], four independent accumulation chains (ipad % 16 == 0
+            // or the tail steps land in the first chains)
+            d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+            for (int i0 = 0; i0 < ipad; i0 += 16) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ii = i0 + 4 * q + lk;
+                    if (i0 + 4 * q < ipad) {
+                        const double av = D[(tj0 + lr) * LDD + ii];
+                        const double bv = (ii <= n) ? basis[ii * KLP + tk0 + lr] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+                    }
+                }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Tb[(tj0 + lk + 4 * v) * LDT + tk0 + lr] = acc[v];
+            for (int v = 0; v < 4; ++v)
+                Tb[(tj0 + lk + 4 * v) * LDT + tk0 + lr] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
         }
         __syncthreads();
 #pragma unroll
-        for (int r0 = 0; r0 < 32; r0 += 4) {   // H[k][l] += sum_r T[r][k] B[jb + r][l]
-            const int jj = jb + r0 + lk;
-            const double av = Tb[(r0 + lk) * LDT + hk0 + lr];
-            const double bv = (jj <= n) ? basis[jj * KLP + hl0 + lr] : 0.0;
-            hacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, hacc, 0, 0, 0);
+        for (int r0 = 0; r0 < 32; r0 += 8) {   // H[k][l] += sum_r T[r][k] B[jb + r][l], two chains
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int jj = jb + r0 + 4 * q + lk;
+                const double av = Tb[(r0 + 4 * q + lk) * LDT + hk0 + lr];
+                const double bv = (jj <= n) ? basis[jj * KLP + hl0 + lr] : 0.0;
+                hacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, hacc[q], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -134,7 +144,7 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int k = hk0 + lk + 4 * v, l = hl0 + lr;
-        if (k < kl && l < kl) grad[p * K + k * kl + l] = bad ? NAN : sqrt_lam[k * kl + l] * hacc[v];
+        if (k < kl && l < kl) grad[p * K + k * kl + l] = bad ? NAN : sqrt_lam[k * kl + l] * (hacc[0][v] + hacc[1][v]);
     }
 }
 

@@ -144,6 +144,29 @@ def test_value_and_grad_c4_full_size_sampled():
         assert np.abs(g[k] - rg).max() <= 1e-8 * np.abs(rg).max()
 
 
+def test_value_and_grad_crowded_column():
+    """Seven observations in one column within one thread's strip of 32 rows (more point sources
+    than the adjoint's residual pass keeps in its per-strip list), beside three elsewhere: the
+    128^2 FP32+refinement gradient of two particles against the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("value_and_grad crowded column")
+    d, _ = load("c4")
+    d = dict(d)
+    d["obs"] = [[32, y] for y in range(17, 24)] + [[11, 11], [43, 53], [53, 21]]
+    d["y"] = [0.03 + 0.001 * k for k in range(len(d["obs"]))]
+    d.pop("G_true_fine", None)
+    op = OProblem(d)
+    N = 2
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    xi = inputs.particles(N, op.K, 33)
+    phi, g, it = gpu_value_and_grad(p, t(xi), smc.SMC_FP32_REFINE)
+    assert (it > 0).all() and smc.smc_status_flags(p) == 0
+    for k in range(N):
+        rphi, rg = value_and_grad(op, xi[k], 128)
+        assert abs(phi[k] / rphi - 1) <= 1e-4
+        assert np.abs(g[k] - rg).max() <= 1e-8 * np.abs(rg).max()
+
+
 def test_gradient_taylor_remainder():
     """|Phi(xi + e d) - Phi(xi) - e g.d| falls as e^2."""
     from paper_2503_16028_amd import smc
