@@ -25,6 +25,7 @@ FP32_VECTOR_PEAK = 157.3e12     # MI355X published FP32 vector peak
 F16_MFMA_PEAK = 2.5e15          # MI355X published dense fp16 and bf16 matrix peak
 HBM_PEAK = 8.0e12               # MI355X HBM3E peak, bytes/s
 LDS_PEAK = 256 * 128 * 2.4e9    # LDS bandwidth: 256 compute units x 128 bytes per clock x 2.4 GHz
+L2_PEAK = 8 * 16 * 128 * 2.4e9  # L2: 8 XCDs x 16 channels x 128 bytes per clock x 2.4 GHz
 
 
 def lds_bytes_per_solve(iters, apps, sweeps, n=GRID):
@@ -45,10 +46,11 @@ COUNTERS = os.path.join(ROOT, "profiles", "cg_onchip_128x32_fastpoisson_c3_count
 SOLVER_SOURCES = [os.path.join(ROOT, "paper_2503_16028_amd", "csrc", f) for f in ("k_solve.hip", "common.hpp")]
 
 
-def measured_traffic(tile):
-    """HBM bytes per solve launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
-    each calibrated against a copy of known size), or None once the solver sources or the tile
-    shape differ from what was profiled."""
+def measured_traffic(tile, field="traffic_bytes_per_launch"):
+    """Bytes per solve launch from the committed counter summary: HBM (FETCH_SIZE and WRITE_SIZE,
+    each calibrated against a copy of known size), or with `field` the L2 request bytes
+    (TCP_TCC_READ_REQ and TCP_TCC_WRITE_REQ times the request sizes a copy shows); None once the
+    solver sources or the tile shape differ from what was profiled."""
     import hashlib
     try:
         fields = dict(l.strip().split(" = ", 1) for l in open(COUNTERS) if " = " in l and l.startswith("    "))
@@ -57,7 +59,7 @@ def measured_traffic(tile):
             h.update(open(f, "rb").read())
         if h.hexdigest() != fields.get("source_sha256") or int(fields.get("tile_rows", -1)) != tile:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[field])
     except (OSError, ValueError, KeyError):
         return None
 
@@ -477,6 +479,7 @@ def main():
         variants["fp64_per_particle_sample"] = "%d particles x %d move, one launch sequence per particle" % (done, nm)
         variants["fp32_refine_batched_moves_per_s"] = value
     traffic = measured_traffic(tile) if fast_poisson else None
+    l2_bytes = measured_traffic(tile, "l2_request_bytes_per_launch") if fast_poisson else None
     # HBM roofline of the solve (the forward solves' target is a fraction of the HBM peak): bytes per
     # launch from the committed FETCH_SIZE/WRITE_SIZE summary of this kernel, over the live launch
     # time.  The streaming byte model of a Jacobi-PCG solve, U (48 I + 20 S + 12) bytes per solve,
@@ -521,6 +524,10 @@ def main():
                      "lds": {"bytes_per_launch": lds_launch, "achieved": lds_launch / (kernel_ms * 1e-3) / 1e12,
                              "peak": LDS_PEAK / 1e12, "unit": "TB/s",
                              "frac": lds_launch / (kernel_ms * 1e-3) / LDS_PEAK},
+                     "l2": None if l2_bytes is None else
+                     {"bytes_per_launch": l2_bytes, "achieved": l2_bytes / (kernel_ms * 1e-3) / 1e12,
+                      "peak": L2_PEAK / 1e12, "unit": "TB/s", "frac": l2_bytes / (kernel_ms * 1e-3) / L2_PEAK,
+                      "counts": "vector-cache requests to L2 (counters), 128-byte reads and 64-byte writes"},
                      "mfma": {"achieved": achieved / 1e12, "peak": F16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                               "frac": achieved / F16_MFMA_PEAK,
                               "counts": "8 n^3 FLOP of dense sine-transform products per preconditioner application"},
