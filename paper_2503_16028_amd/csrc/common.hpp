@@ -242,11 +242,10 @@ hipError_t launch_stage_onchip(int n, int rows, const SolveArgs& a, const StageA
                                const void* S, const float* lam, unsigned long long* counters, int grid,
                                hipStream_t s);
 // The counters workspace: [0, 2) the persistent launches' fetch and done counters; then per grid
-// l of a level map its own pair at COUNTER_LIST + 2 l, and the segment of the work list that holds
-// its particles, start and count, at COUNTER_SEG + 2 l (grid MAX_LEVELS: the particles with no
-// grid, parked or out of range, which come last).
-constexpr int COUNTER_LIST = 2;
-constexpr int COUNTER_SEG = COUNTER_LIST + 2 * MAX_LEVELS;
+// l of a level map the segment of the work list that holds its particles, start and count, at
+// COUNTER_SEG + 2 l (grid MAX_LEVELS: the particles with no grid, parked or out of range, which
+// come last).
+constexpr int COUNTER_SEG = 2;
 constexpr int N_COUNTERS = COUNTER_SEG + 2 * (MAX_LEVELS + 1);
 hipError_t launch_plan(int64_t N, const int32_t* level, const LevelTable& lt, int32_t* list,
                        unsigned long long* counters, int32_t* flags, hipStream_t s);

@@ -1705,60 +1705,42 @@ hipError_t launch_solve_mixed(int prec, bool dst, int64_t N, const SolveArgs& a,
 
 // ------------------------------------------------------------------ one launch per grid of a level map
 // plan_kernel leaves grid l's particles in list[start .. start + count) (start and count at
-// COUNTER_SEG + 2 l); each grid is solved by a persistent launch in the workgroup shape of its
-// single-grid launch (the same body, so the same bits), taking items from its own counter pair; the
-// last workgroup to leave zeroes the pair for the next launch or graph replay.
-template <typename F>
-__device__ __forceinline__ void list_loop(unsigned long long* counters, int lvl, const int32_t* __restrict__ list,
-                                          unsigned long long* item_s, F&& body) {
+// COUNTER_SEG + 2 l); each grid is solved by a launch of N workgroups in the shape of its
+// single-grid launch, workgroup k taking list entry start + k and the ones beyond the count
+// leaving at once.  The body is the single-grid kernel's (the same bits), and without a fetch loop
+// around it the compiler allocates its registers as in that kernel (a persistent loop spilled more
+// and, at 64^2, held more registers than two workgroups per compute unit leave).
+__device__ __forceinline__ int64_t list_item(const unsigned long long* counters, int lvl,
+                                             const int32_t* __restrict__ list) {
     const int64_t start = __builtin_amdgcn_readfirstlane((int)counters[COUNTER_SEG + 2 * lvl]);
     const int64_t count = __builtin_amdgcn_readfirstlane((int)counters[COUNTER_SEG + 2 * lvl + 1]);
-    unsigned long long* ctr = counters + COUNTER_LIST + 2 * lvl;
-    for (;;) {
-        if (threadIdx.x == 0) *item_s = atomicAdd(&ctr[0], 1ull);
-        __syncthreads();
-        // wave-uniform item: the loop exit must be a uniform branch (see solve_mixed_kernel)
-        const int64_t item =
-            __builtin_amdgcn_readfirstlane((int)(*item_s < (unsigned long long)count ? *item_s : count));
-        __syncthreads();
-        if (item >= count) break;
-        const int64_t p = __builtin_amdgcn_readfirstlane(list[start + item]);
-        body(p);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const unsigned long long done = atomicAdd(&ctr[1], 1ull);
-        if (done == (unsigned long long)gridDim.x - 1ull) {   // every workgroup has stopped fetching
-            ctr[0] = 0;
-            ctr[1] = 0;
-        }
-    }
+    if ((int64_t)blockIdx.x >= count) return -1;
+    return __builtin_amdgcn_readfirstlane(list[start + blockIdx.x]);
 }
 
 template <typename T, int NN, int R>
 __global__ __launch_bounds__(NN * NN / R) void solve_list_onchip(SolveArgs a, const int32_t* __restrict__ list,
-                                                                 unsigned long long* counters, int lvl,
+                                                                 const unsigned long long* counters, int lvl,
                                                                  const int32_t* __restrict__ obs,
                                                                  const _Float16* __restrict__ Stab,
                                                                  const float* __restrict__ lamtab) {
     __shared__ __align__(16) unsigned char smem[onchip_smem<T, NN, R, true>()];
     __shared__ SolveShared sh;
-    __shared__ unsigned long long item_s;
-    list_loop(counters, lvl, list, &item_s,
-              [&](int64_t p) { cg_onchip_body<T, NN, R, true, false>(a, p, obs, smem, sh, Stab, lamtab); });
+    const int64_t p = list_item(counters, lvl, list);
+    if (p < 0) return;
+    cg_onchip_body<T, NN, R, true, false>(a, p, obs, smem, sh, Stab, lamtab);
 }
 
 template <typename T, int NN>
 __global__ __launch_bounds__(1024) void solve_list_global(SolveArgs a, const int32_t* __restrict__ list,
-                                                          unsigned long long* counters, int lvl,
+                                                          const unsigned long long* counters, int lvl,
                                                           const int32_t* __restrict__ obs,
                                                           const _Float16* __restrict__ Stab,
                                                           const float* __restrict__ lamtab) {
     __shared__ SolveShared sh;
-    __shared__ unsigned long long item_s;
-    list_loop(counters, lvl, list, &item_s, [&](int64_t p) {
-        cg_global_body<T, false, true, NN>(a, p, NN, obs, sh, reinterpret_cast<_Float16*>(g_mixed_smem), Stab, lamtab);
-    });
+    const int64_t p = list_item(counters, lvl, list);
+    if (p < 0) return;
+    cg_global_body<T, false, true, NN>(a, p, NN, obs, sh, reinterpret_cast<_Float16*>(g_mixed_smem), Stab, lamtab);
 }
 
 // The particles with no grid (parked or out of range): the outputs of a rejected proposal.
@@ -1777,6 +1759,7 @@ __global__ __launch_bounds__(256) void reject_list_kernel(SolveArgs a, const int
 
 hipError_t launch_solve_levels(int prec, int64_t N, const SolveArgs& a, const LevelTable& lt, const int* rows,
                                const int32_t* list, unsigned long long* counters, int n_cu, hipStream_t s) {
+    (void)n_cu;
     if (N <= 0) return hipSuccess;
     int order[MAX_LEVELS];   // finest grid first, as the list is
     for (int l = 0; l < lt.n_levels; ++l) order[l] = l;
@@ -1785,7 +1768,7 @@ hipError_t launch_solve_levels(int prec, int64_t N, const SolveArgs& a, const Le
             if (lt.n[order[j]] > lt.n[order[i]]) std::swap(order[i], order[j]);
     SolveArgs b = a;
     if (prec == SMC_FP64) b.tol_inner = 0.1 * a.tol64;   // FP64 CG to 0.1 tol64 in one sweep, as single-grid
-    const dim3 g1((unsigned)n_cu), g4((unsigned)(4 * n_cu));
+    const dim3 g1((unsigned)N), g4((unsigned)N);   // at most N particles per grid
     for (int k = 0; k < lt.n_levels; ++k) {
         const int l = order[k], n = lt.n[l];
         const _Float16* S = reinterpret_cast<const _Float16*>(lt.S[l]);
