@@ -161,8 +161,10 @@ int smc_synthesize(smc_problem p, int64_t N, const double* xi, int32_t level, do
                    smc_stream stream);
 
 /* Forward map G = F(u(xi)) for N particles (one PDE solve each, Sec. 3.2).
- *   level  [N] device, grid index per particle, or NULL for grid 0.  With a level map all
- *          particles run in one persistent launch (2D, grids of 64, 128 and 256 intervals);
+ *   level  [N] device, grid index per particle, or NULL for grid 0.  With a level map the
+ *          particles are grouped by grid on the device and each grid is solved by a launch in
+ *          the shape of its single-grid launch, with the same results (2D, grids of 64, 128 and
+ *          256 intervals; with the Jacobi-only preconditioner one persistent launch serves all);
  *          a particle whose level is out of range gets G = NaN, iters = -1 and sets
  *          SMC_FLAG_BADLEVEL; level SMC_LEVEL_PARKED gives the same outputs without a solve
  *          and without the flag
@@ -365,8 +367,9 @@ int smc_precond_apply(smc_problem p, int32_t level, int64_t N, const float* r, f
  *   smc_tile_candidates  the shapes the library has for grid n (rows[8] out, *count out);
  *                        the first is the default; grid 256 has the single entry 0
  *   smc_set_tile         choose one for grid `level` (0 = default); smc_get_tile reads it back.
- *                        The default of the forward-and-adjoint solve (smc_value_and_grad,
- *                        smc_pcnl_move) at 128^2 is 16 rows; a shape set here applies to both
+ *                        The forward-and-adjoint solve (smc_value_and_grad, smc_pcnl_move) at
+ *                        128^2 runs as two launches of the 32-row shape by default, and as one
+ *                        launch of both passes with 16 rows set here
  *   smc_autotune         time every candidate on N synthetic prior particles (drawn by the
  *                        library into its own workspace), reps timed launches each after one
  *                        warm-up, keep the fastest; *rows out, ms[count] out (may be NULL): mean

@@ -156,8 +156,7 @@ class MixedSampler:
     temperature, increment, step size, resampling, mixture and evidence, exactly as SMCSampler
     would run it on that grid alone.  Each stage, every sampler still below temperature 1
     re-weights, resamples and fits its mixture on its own rows; then one smc_gmpcn_stage (captured
-    once as a HIP graph) moves all of them, one persistent launch per move serving the three grids
-    at once.  A sampler whose temperature reaches 1 parks its particles (level SMC_LEVEL_PARKED):
+    once as a HIP graph) moves all of them, each move's solves one launch per grid.  A sampler whose temperature reaches 1 parks its particles (level SMC_LEVEL_PARKED):
     its final cloud is kept as it is and costs nothing in later stages.
 
     Random numbers: moves at counter s * 2^20 + m, with a particle's global index as its word, so
