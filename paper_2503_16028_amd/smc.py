@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libsmc.so")
 
 SMC_OK = 0
+SMC_E_INVAL, SMC_E_HIP, SMC_E_NOCONV, SMC_E_STALL, SMC_E_NONFINITE, SMC_E_NOMEM = -1, -2, -3, -4, -5, -6
 SMC_FP64 = 0
 SMC_FP32_REFINE = 1
 FLAG_NOCONV, FLAG_STALL, FLAG_NONFINITE, FLAG_BADWEIGHTS, FLAG_BADLEVEL, FLAG_BADPARAM = 1, 2, 4, 8, 16, 32
