@@ -109,14 +109,53 @@ class SMCSampler:
         if tau < 1.0 and float(self.h.item()) == 0.0:
             raise RuntimeError("temperature bisection stalled at stage %d (tau = %.17g)" % (self.stage, tau))
 
-    def run(self, max_stages=500):
-        self.initialise()
-        for _ in range(max_stages):
-            if self.step() >= 1.0:
+    def run(self, max_stages=500, stop_after=None):
+        """Run to temperature 1 (at most max_stages stages in all).  A sampler restored with
+        load_state_dict continues where the saved one stopped; stop_after ends this call after that
+        many stages (for a checkpoint) with the sampler still below temperature 1."""
+        if self.stage == 0:
+            self.initialise()
+        done = 0
+        while float(self.tau.item()) < 1.0 and self.stage < max_stages:
+            if stop_after is not None and done >= stop_after:
                 break
+            self.step()
+            done += 1
         if int(self.flags.item()) & smc.FLAG_STALL:
             raise RuntimeError("temperature bisection stalled")
         return dict(xi=self.xi, phi=self.phi, log_Z=self.log_Z, history=self.history)
+
+    # ---------------------------------------------------------------- checkpoint and resume
+    # Every random number of a stage is keyed by (seed, stage, move, particle), so a run restored
+    # from its state after any stage continues with the same bits as one never interrupted.
+    def _config(self):
+        return dict(kind=type(self).__name__, N=self.N, M=self.M, n_moves=self.n_moves, prec=int(self.prec),
+                    seed=self.seed, ess_frac=float(self.ess_frac), fit_iters=self.fit_iters, K=int(self.p.K))
+
+    def state_dict(self):
+        """The sampler's state between stages: particles, potentials, temperature, evidence, step
+        size, stage counter, device flags and history, on the host."""
+        torch.cuda.synchronize(self.dev)
+        return dict(config=self._config(), stage=self.stage, beta=self.beta, log_Z=self.log_Z,
+                    history=[dict(h) for h in self.history], xi=self.xi.cpu(), phi=self.phi.cpu(),
+                    tau=self.tau.cpu(), flags=self.flags.cpu())
+
+    def load_state_dict(self, state):
+        if state["config"] != self._config():
+            raise ValueError("checkpoint of a different sampler: %r, not %r" % (state["config"], self._config()))
+        self.stage, self.beta, self.log_Z = int(state["stage"]), float(state["beta"]), float(state["log_Z"])
+        self.history = [dict(h) for h in state["history"]]
+        self.xi.copy_(state["xi"].to(self.dev))
+        self.phi.copy_(state["phi"].to(self.dev))
+        self.tau.copy_(state["tau"].to(self.dev))
+        self.flags.copy_(state["flags"].to(self.dev))
+        torch.cuda.synchronize(self.dev)
+
+    def save(self, path):
+        torch.save(self.state_dict(), path)
+
+    def load(self, path):
+        self.load_state_dict(torch.load(path, weights_only=True))
 
 
 class SMCGMSampler(SMCSampler):
