@@ -92,12 +92,33 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
     const int hk0 = (wave & 1) * 16, hl0 = (wave >> 1) * 16;   // this wave's H tile (k, l)
     d4 hacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int jb = 0; jb < np1; jb += 32) {
-        for (int t = threadIdx.x; t < 32 * ipad; t += 256) {
+        if (du) {   // formed by the adjoint solve: thread t holds column t (and t + 256) of the 32 rows,
+                    // all 32 loads in flight before the first store
+            const double* dp = du + p * du_stride;
+            const int i = threadIdx.x;
+            double v[32];
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+                const int j = jb + r;
+                const bool ok = j <= n && i <= n;
+                v[r] = dp[ok ? j * np1 + i : 0];
+                v[r] = ok ? v[r] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 32; ++r)
+                if (i < ipad) D[r * LDD + i] = v[r];
+            if (i + 256 < ipad) {   // 257 nodes per row at n = 256
+#pragma unroll 4
+                for (int r = 0; r < 32; ++r) {
+                    const int j = jb + r, i2 = i + 256;
+                    D[r * LDD + i2] = (j <= n && i2 <= n) ? dp[j * np1 + i2] : 0.0;
+                }
+            }
+        }
+        for (int t = threadIdx.x; !du && t < 32 * ipad; t += 256) {
             const int r = t / ipad, i = t % ipad, j = jb + r;
             double v = 0.0;
-            if (j <= n && i <= n && du) {
-                v = du[p * du_stride + j * np1 + i];   // formed by the adjoint solve
-            } else if (j <= n && i <= n) {
+            if (j <= n && i <= n) {
                 const double wP = at(wp, j, i), lP = at(lp, j, i);
                 double acc = 0.0;
                 if (i > 0) acc += ep[j * np1 + i - 1] * (lP - at(lp, j, i - 1)) * (wP - at(wp, j, i - 1));
