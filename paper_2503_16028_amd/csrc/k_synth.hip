@@ -3,8 +3,8 @@
 // 2D: the cosine basis is separable, phi_kl(x_i, y_j) = B[i][k] B[j][l], so per particle
 //     u[j][i] = sum_k sum_l B[i][k] X[k][l] B[j][l],   X[k][l] = sqrt(lambda_kl) xi_kl,
 // i.e. two small dense products T = X B^T (32 x (n+1)) and U = T^T B^T ((n+1) x (n+1)).
-// Both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64) with the operands staged in
-// LDS; the epilogue optionally returns exp(u/2), the nodal factor of the geometric-mean face
+// Both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64), X and T in LDS (T written over X)
+// and B read straight into registers; the epilogue optionally returns exp(u/2), the nodal factor of the geometric-mean face
 // coefficient exp((u_P + u_Q)/2) = exp(u_P/2) exp(u_Q/2) of the forward operator.
 #include "common.hpp"
 #include "synth_body.hpp"
@@ -184,8 +184,7 @@ hipError_t launch_gradsynth2d(const double* e, int64_t e_stride, const double* w
 hipError_t launch_synth2d(const double* xi, int K, int kl, const double* sqrt_lam, const double* basis, int n,
                           double* out, int64_t out_stride, int64_t N, bool exp_half, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const int npad = (n + 1 + 15) & ~15;
-    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
+    const size_t lds = sizeof(double) * (size_t)synth2d_lds_doubles(n);
     if (exp_half)
         synth2d_kernel<true><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, basis, n, out, out_stride);
     else
@@ -199,8 +198,7 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
     if (N <= 0) return hipSuccess;
     int nmax = 0;
     for (int l = 0; l < lt.n_levels; ++l) nmax = lt.n[l] > nmax ? lt.n[l] : nmax;
-    const int npad = (nmax + 1 + 15) & ~15;
-    const size_t lds = sizeof(double) * ((size_t)KLP * (KLP + 1) + (size_t)KLP * npad);
+    const size_t lds = sizeof(double) * (size_t)synth2d_lds_doubles(nmax);
     if (exp_half)
         synth2d_levels_kernel<true><<<dim3((unsigned)N), dim3(SYN_THREADS), lds, s>>>(xi, K, kl, sqrt_lam, lt, level, out,
                                                                              out_stride);
@@ -213,8 +211,8 @@ hipError_t launch_synth2d_levels(const double* xi, int K, int kl, const double* 
 // Dynamic LDS limits of the synthesis kernels, set once for the largest grid (256 intervals), so
 // that no launch needs an attribute call (launches may be captured into graphs).
 hipError_t prepare_kernels() {
-    constexpr int npad = (256 + 1 + 15) & ~15, ipad = (256 + 1 + 3) & ~3;
-    const int synth = (int)sizeof(double) * (KLP * (KLP + 1) + KLP * npad);
+    constexpr int ipad = (256 + 1 + 3) & ~3;
+    const int synth = (int)sizeof(double) * synth2d_lds_doubles(256);
     const int grad = (int)sizeof(double) * (32 * (ipad + 1) + 32 * (KLP + 1));
     const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
     hipError_t e = hipSuccess;
