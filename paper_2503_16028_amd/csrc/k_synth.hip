@@ -61,6 +61,9 @@ __global__ __launch_bounds__(256) void synth1d_kernel(const double* __restrict__
 // dU is formed 32 grid rows at a time in LDS (or read from `du`, where the on-chip adjoint solve
 // formed it already) and contracted on the FP64 matrix cores:
 //   T[j][k] = sum_i dU[j][i] B[i][k] for the block's rows j, then H[k][l] += sum_j T[j][k] B[j][l].
+// With B[n - i][k] = (-1)^k B[i][k] the first product runs over the first half of the row only:
+// even k take dU[j][i] + dU[j][n - i], odd k dU[j][i] - dU[j][n - i] (i < n/2), and the middle
+// node once.  The blocks cover rows 0 .. n-1; row n is summed apart on the vector units.
 // A particle whose solves did not converge (iters < 0) gets a NaN gradient.
 __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restrict__ e, int64_t e_stride,
                                                           const double* __restrict__ w, int64_t w_stride,
@@ -72,6 +75,7 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
                                                           int64_t du_stride) {
     extern __shared__ double smem[];
     const int np1 = n + 1;
+    const int h = n >> 1;
     const int ipad = (np1 + 3) & ~3;
     const int LDD = ipad + 1;
     constexpr int LDT = KLP + 1;
@@ -81,26 +85,37 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
     const double* ep = e + p * e_stride;
     const double* wp = w + p * w_stride;
     const double* lp = lam + p * lam_stride;
+    const double* dp = du ? du + p * du_stride : nullptr;
     const double scale = -0.5 * (double)n * (double)n;
     // interior values are stored at (j - 1) n + (i - 1); boundary nodes are zero
     auto at = [&](const double* v, int j, int i) -> double {
         return (i >= 1 && i < n && j >= 1 && j < n) ? v[(j - 1) * n + (i - 1)] : 0.0;
     };
+    // dPhi/du at node (j, i) from e, w and lam (when the adjoint solve did not form it)
+    auto form = [&](int j, int i) -> double {
+        const double wP = at(wp, j, i), lP = at(lp, j, i);
+        double acc = 0.0;
+        if (i > 0) acc += ep[j * np1 + i - 1] * (lP - at(lp, j, i - 1)) * (wP - at(wp, j, i - 1));
+        if (i < n) acc += ep[j * np1 + i + 1] * (lP - at(lp, j, i + 1)) * (wP - at(wp, j, i + 1));
+        if (j > 0) acc += ep[(j - 1) * np1 + i] * (lP - at(lp, j - 1, i)) * (wP - at(wp, j - 1, i));
+        if (j < n) acc += ep[(j + 1) * np1 + i] * (lP - at(lp, j + 1, i)) * (wP - at(wp, j + 1, i));
+        return scale * ep[j * np1 + i] * acc;
+    };
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int tj0 = (wave >> 1) * 16, tk0 = (wave & 1) * 16;   // this wave's T tile (block rows, k)
+    const int tj0 = (wave >> 1) * 16, par = wave & 1;          // this wave's T tile: 16 block rows, k = 2 lr + par
     const int hk0 = (wave & 1) * 16, hl0 = (wave >> 1) * 16;   // this wave's H tile (k, l)
+    const int nsteps = (h + 1 + 3) >> 2;                       // first-product steps over i = 0 .. h
     d4 hacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-    for (int jb = 0; jb < np1; jb += 32) {
-        if (du) {   // formed by the adjoint solve: thread t holds column t (and t + 256) of the 32 rows,
+    for (int jb = 0; jb < n; jb += 32) {
+        if (dp) {   // formed by the adjoint solve: thread t holds column t (and t + 256) of the 32 rows,
                     // all 32 loads in flight before the first store
-            const double* dp = du + p * du_stride;
             const int i = threadIdx.x;
             double v[32];
 #pragma unroll
             for (int r = 0; r < 32; ++r) {
                 const int j = jb + r;
-                const bool ok = j <= n && i <= n;
+                const bool ok = j < n && i <= n;
                 v[r] = dp[ok ? j * np1 + i : 0];
                 v[r] = ok ? v[r] : 0.0;
             }
@@ -111,42 +126,36 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
 #pragma unroll 4
                 for (int r = 0; r < 32; ++r) {
                     const int j = jb + r, i2 = i + 256;
-                    D[r * LDD + i2] = (j <= n && i2 <= n) ? dp[j * np1 + i2] : 0.0;
+                    D[r * LDD + i2] = (j < n && i2 <= n) ? dp[j * np1 + i2] : 0.0;
                 }
             }
         }
-        for (int t = threadIdx.x; !du && t < 32 * ipad; t += 256) {
+        for (int t = threadIdx.x; !dp && t < 32 * ipad; t += 256) {
             const int r = t / ipad, i = t % ipad, j = jb + r;
-            double v = 0.0;
-            if (j <= n && i <= n) {
-                const double wP = at(wp, j, i), lP = at(lp, j, i);
-                double acc = 0.0;
-                if (i > 0) acc += ep[j * np1 + i - 1] * (lP - at(lp, j, i - 1)) * (wP - at(wp, j, i - 1));
-                if (i < n) acc += ep[j * np1 + i + 1] * (lP - at(lp, j, i + 1)) * (wP - at(wp, j, i + 1));
-                if (j > 0) acc += ep[(j - 1) * np1 + i] * (lP - at(lp, j - 1, i)) * (wP - at(wp, j - 1, i));
-                if (j < n) acc += ep[(j + 1) * np1 + i] * (lP - at(lp, j + 1, i)) * (wP - at(wp, j + 1, i));
-                v = scale * ep[j * np1 + i] * acc;
-            }
-            D[r * LDD + i] = v;
+            D[r * LDD + i] = (j < n && i <= n) ? form(j, i) : 0.0;
         }
         __syncthreads();
-        {   // T[r][k] = sum_i D[r][i] B[i][k], four independent accumulation chains (ipad % 16 == 0
-            // or the tail steps land in the first chains)
+        {   // T[r][k] = sum_{i <= h} A[r][i] B[i][k] with A = dU[r][i] +- dU[r][n - i] (i < h) or
+            // dU[r][h] (i = h); four independent accumulation chains
+            const double sgn = par ? -1.0 : 1.0;
+            const double* Dr = D + (tj0 + lr) * LDD;
             d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-            for (int i0 = 0; i0 < ipad; i0 += 16) {
+            for (int s0 = 0; s0 < nsteps; s0 += 4) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int ii = i0 + 4 * q + lk;
-                    if (i0 + 4 * q < ipad) {
-                        const double av = D[(tj0 + lr) * LDD + ii];
-                        const double bv = (ii <= n) ? basis[ii * KLP + tk0 + lr] : 0.0;
+                    if (s0 + q < nsteps) {
+                        const int ii = 4 * (s0 + q) + lk;
+                        const int ic = ii < h ? ii : h;                  // clamped, selected below
+                        const double d0 = Dr[ic], d1 = Dr[n - ic];
+                        const double av = ii < h ? fma(sgn, d1, d0) : (ii == h ? d0 : 0.0);
+                        const double bv = basis[ic * KLP + 2 * lr + par];
                         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
                     }
                 }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Tb[(tj0 + lk + 4 * v) * LDT + tk0 + lr] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+                Tb[(tj0 + lk + 4 * v) * LDT + 2 * lr + par] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
         }
         __syncthreads();
 #pragma unroll
@@ -155,17 +164,32 @@ __global__ __launch_bounds__(256) void gradsynth2d_kernel(const double* __restri
             for (int q = 0; q < 2; ++q) {
                 const int jj = jb + r0 + 4 * q + lk;
                 const double av = Tb[(r0 + 4 * q + lk) * LDT + hk0 + lr];
-                const double bv = (jj <= n) ? basis[jj * KLP + hl0 + lr] : 0.0;
+                const double bv = (jj < n) ? basis[jj * KLP + hl0 + lr] : 0.0;
                 hacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, hacc[q], 0, 0, 0);
             }
         }
         __syncthreads();
     }
+    // row n: T[n][k] = sum_i dU[n][i] B[i][k] as eight strided partial sums per k, added in a
+    // fixed order, then H[k][l] += T[n][k] B[n][l]
+    for (int i = threadIdx.x; i <= n; i += 256) D[i] = dp ? dp[n * np1 + i] : form(n, i);
+    __syncthreads();
+    {
+        const int k = threadIdx.x & 31, c = threadIdx.x >> 5;
+        double s = 0.0;
+        for (int i = c; i <= n; i += 8) s = fma(D[i], basis[i * KLP + k], s);
+        Tb[c * LDT + k] = s;
+    }
+    __syncthreads();
     const bool bad = iters && iters[p] < 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int k = hk0 + lk + 4 * v, l = hl0 + lr;
-        if (k < kl && l < kl) grad[p * K + k * kl + l] = bad ? NAN : sqrt_lam[k * kl + l] * (hacc[0][v] + hacc[1][v]);
+        double tn = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) tn += Tb[c * LDT + k];
+        const double g = fma(tn, basis[n * KLP + l], hacc[0][v] + hacc[1][v]);
+        if (k < kl && l < kl) grad[p * K + k * kl + l] = bad ? NAN : sqrt_lam[k * kl + l] * g;
     }
 }
 
