@@ -37,6 +37,7 @@ __device__ __forceinline__ void synth2d_body(const double* __restrict__ xp, int 
     // Products of the first stage per wave, held in registers until X is dead: 2 n / 16 units
     // (n <= 256, the largest 2D grid) over at least 8 waves
     constexpr int MAXU = 2;
+    static_assert(NWAVES >= 8, "first-stage units of a 256-interval grid: 2 per wave need 8 waves");
     double* X = smem;                           // [KLP][LD], the first stage's operand
     double* T = smem;                           // [KLP][n + 1], written over X after the first stage
     auto out = [&](double v) { return EXPHALF ? exp(0.5 * v) : v; };
