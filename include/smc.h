@@ -61,7 +61,7 @@ typedef enum {
 
 typedef void* smc_stream; /* hipStream_t */
 typedef struct smc_problem_s* smc_problem;
-typedef struct smc_graph_s* smc_graph;   /* an instantiated, replayable move stage */
+typedef struct smc_graph_s* smc_graph;   /* an instantiated, replayable stage */
 
 /* Problem definition (host memory; copied by smc_problem_create).
  * Forward map (Sec. 3.2, eq. (example2:PDE), gradient on the state):
@@ -240,6 +240,54 @@ int smc_stage_graph_create(smc_problem p, int64_t N, const int32_t* level, const
                            smc_stream stream, smc_graph* out);
 int smc_stage_graph_launch(smc_graph g, smc_stream stream);
 void smc_stage_graph_destroy(smc_graph g);
+
+/* A whole tempering stage of G independent samplers captured into one graph (Alg. 1 with the
+ * pCN-GM mutation of Alg. 2): for every group g, the tempering step (App. C), systematic
+ * resampling, the gather of the selected rows, and (M > 1) the mixture fit; then n_moves
+ * pCN-GM moves of all groups (as smc_gmpcn_stage); then a rule on the device that records the
+ * stage, adapts each group's step size and parks a group that has reached temperature 1.
+ * Every per-stage value lives in device memory, so each smc_stage_graph_launch runs the next
+ * stage with no host work; the host reads tau to stop (or parks nothing and stops by itself).
+ * Group g owns the rows [off_g, off_g + counts[g]), off_g = counts[0] + ... + counts[g-1]; with
+ * a level map (G = the problem's n_levels, level[row] = g at the start) group g solves on grid g,
+ * without one (G = 1) every row is group 0.  Random numbers: stage s (s = *ctr / stride) moves
+ * with counter s stride + m, and group g resamples and seeds its fit with counter s stride + g,
+ * as smc_philox_u53 and smc_gm_fit would with those counters: the graph gives the bits of the
+ * same calls made one by one.
+ * A group at temperature 1 still passes through tempering (uniform weights), resampling (then the
+ * identity) and its fit, which leave its rows as they are; its moves are skipped once it is
+ * parked, and it is recorded no more.  The rule, per running group: rate = accepted moves /
+ * (rows * max(1, n_moves)); record[s-1][g][0..4] = tau, h, beta of the stage, rate, log-evidence
+ * increment (rows past max_stages are not written); beta doubles (at most 1) above a rate of 0.3
+ * and halves below 0.15; with a level map, a group with tau >= 1 sets its rows to
+ * SMC_LEVEL_PARKED.  Then *ctr += stride.
+ * All arrays are device arrays that stay valid while the graph exists; the graph reads and
+ * writes them in place and uses the problem's workspace (launches must not overlap other calls
+ * on the problem).  For callers that replay stages without host work between them. */
+typedef struct {
+    int32_t n_groups;                /* G: 1, or the problem's n_levels with a level map */
+    int64_t counts[4];               /* host: rows of each group (the first G entries) */
+    int32_t M, kr, fit_iters;        /* mixture components (M = 1: the given single component,
+                                        no fit), active modes, EM steps of the fit */
+    int32_t n_moves, max_stages;     /* moves per stage; rows of `record` */
+    double ess_frac, var_floor;      /* ESS target fraction; variance floor of the fit */
+    uint64_t seed, stride;           /* random stream; counter spacing of the stages */
+    double* xi; double* phi;         /* [N][K], [N]: the particles and their potentials */
+    double* xi2; double* phi2;       /* [N][K], [N]: gather scratch */
+    double* W; int32_t* idx;         /* [N]: weights and resampling indices */
+    double* tau; double* tau_new;    /* [G]: temperatures */
+    double* h; double* log_z;        /* [G]: last step and log-evidence increment */
+    double* beta;                    /* [G]: step sizes, adapted by the rule */
+    double* logw; double* mean; double* scale;   /* [G][M], [G][M][kr], [G][M][kr] */
+    uint64_t* ctr;                   /* [1]: s * stride during stage s (start it at stride) */
+    int32_t* level;                  /* [N] level map, or NULL for G = 1 */
+    int32_t* n_acc;                  /* [N]: accepted moves of the stage */
+    double* record;                  /* [max_stages][G][5] */
+    int32_t* flags;                  /* status word of tempering and resampling (may be NULL) */
+} smc_sampler_graph_desc;
+
+int smc_sampler_graph_create(smc_problem p, const smc_sampler_graph_desc* d, int32_t prec, smc_stream stream,
+                             smc_graph* out);
 
 /* Forward solve that keeps its FP64 solution (the forward state of the adjoint gradient), on
  * grid 0 of a 2D problem: as smc_forward_batch, and w[N][n][n] out with element [g][c] the

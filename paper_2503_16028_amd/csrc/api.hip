@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "stage_graph.hpp"
 
 using namespace smc;
 
@@ -966,6 +967,120 @@ extern "C" void smc_stage_graph_destroy(smc_graph g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+// The launches of one whole tempering stage (arguments already checked), in the order the
+// samplers make the same calls one by one.
+static int sampler_stage(smc_problem_s* p, const smc_sampler_graph_desc* d, int32_t prec, const int64_t* off,
+                         int64_t N, hipStream_t s) {
+    const Problem& P = p->P;
+    const int G = d->n_groups, K = P.K, M = d->M, kr = d->kr;
+    const uint64_t* ctr = d->ctr;
+    for (int g = 0; g < G; ++g) {
+        const int64_t o = off[g], n = d->counts[g];
+        HIPCHK(launch_temper(n, d->phi + o, d->tau + g, d->ess_frac, d->h + g, d->tau_new + g, d->W + o,
+                             d->log_z + g, d->flags, s));
+        HIPCHK(launch_resample_ctr(n, d->W + o, d->seed, ctr, (uint64_t)g, d->idx + o, d->flags, s));
+        HIPCHK(launch_gather(n, K, d->idx + o, d->xi + o * K, d->phi + o, d->xi2 + o * K, d->phi2 + o, s));
+        HIPCHK(hipMemcpyAsync(d->xi + o * K, d->xi2 + o * K, sizeof(double) * n * K, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(d->phi + o, d->phi2 + o, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(d->tau + g, d->tau_new + g, sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (M > 1) {
+            FitWorkspace w{P.ws_fit_d2, P.ws_fit_par, P.ws_fit_part};
+            HIPCHK(launch_gm_fit_ctr(n, K, kr, P.active, d->xi + o * K, M, d->fit_iters, d->var_floor, d->seed, ctr,
+                                     (uint64_t)g, w, P.ws_fit_centers, d->logw + (int64_t)g * M,
+                                     d->mean + (int64_t)g * M * kr, d->scale + (int64_t)g * M * kr, s));
+        }
+    }
+    smc_stage st{};
+    st.n_groups = G;
+    st.M = M;
+    st.kr = kr;
+    st.logw = d->logw;
+    st.mean = d->mean;
+    st.scale = d->scale;
+    st.beta = d->beta;
+    st.tau = d->tau;
+    st.ctr = ctr;
+    st.seed = d->seed;
+    MoveParams q;
+    if (int r = stage_params(P, &st, d->level, q)) return r;
+    if (int r = move_loop(p, N, q, d->n_moves, d->level, prec, d->xi, d->phi, d->n_acc, s)) return r;
+    StageRule rule;
+    rule.G = G;
+    for (int g = 0; g < G; ++g) {
+        rule.off[g] = off[g];
+        rule.count[g] = d->counts[g];
+    }
+    rule.n_moves = d->n_moves;
+    rule.n_acc = d->n_acc;
+    rule.tau = d->tau;
+    rule.h = d->h;
+    rule.log_z = d->log_z;
+    rule.beta = d->beta;
+    rule.level = d->level;
+    rule.ctr = d->ctr;
+    rule.stride = d->stride;
+    rule.record = d->record;
+    rule.max_stages = d->max_stages;
+    HIPCHK(launch_stage_rule(rule, s));
+    return SMC_OK;
+}
+
+extern "C" int smc_sampler_graph_create(smc_problem p, const smc_sampler_graph_desc* d, int32_t prec,
+                                        smc_stream stream, smc_graph* out) {
+    if (!p || !d || !out) return fail(SMC_E_INVAL, "problem, desc and out must not be NULL");
+    if (!stream) return fail(SMC_E_INVAL, "graph capture needs a created stream, not the null stream");
+    const Problem& P = p->P;
+    const int G = d->n_groups;
+    if (G != (d->level ? P.n_levels : 1))
+        return fail(SMC_E_INVAL, "n_groups (%d) must be %d (%s)", G, d->level ? P.n_levels : 1,
+                    d->level ? "the problem's grid count with a level map" : "1 without a level map");
+    int64_t off[MAX_LEVELS] = {}, N = 0;
+    for (int g = 0; g < G; ++g) {
+        if (d->counts[g] < 1) return fail(SMC_E_INVAL, "counts[%d] must be >= 1", g);
+        off[g] = N;
+        N += d->counts[g];
+    }
+    if (int r = check_n(P, N)) return r;
+    if (N > (1ll << 24)) return fail(SMC_E_INVAL, "at most 2^24 particles");
+    if (d->M < 1 || d->M > MAX_M) return fail(SMC_E_INVAL, "M must be 1..%d", MAX_M);
+    if (d->kr != P.kr) return fail(SMC_E_INVAL, "kr (%d) differs from the problem's kr (%d)", d->kr, P.kr);
+    if (d->M > 1 && (d->fit_iters < 0 || d->fit_iters > 100000))
+        return fail(SMC_E_INVAL, "fit_iters must be 0..100000");
+    if (d->M > 1 && (!(d->var_floor > 0.0) || !std::isfinite(d->var_floor)))
+        return fail(SMC_E_INVAL, "var_floor must be positive");
+    if (!(d->ess_frac > 0.0 && d->ess_frac <= 1.0)) return fail(SMC_E_INVAL, "ess_frac must be in (0, 1]");
+    if (d->stride < 1 || d->max_stages < 0) return fail(SMC_E_INVAL, "stride must be >= 1 and max_stages >= 0");
+    if (!d->xi || !d->phi || !d->xi2 || !d->phi2 || !d->W || !d->idx || !d->tau || !d->tau_new || !d->h ||
+        !d->log_z || !d->beta || !d->logw || !d->mean || !d->scale || !d->ctr || !d->n_acc ||
+        (d->max_stages > 0 && !d->record))
+        return fail(SMC_E_INVAL, "device arrays must not be NULL (level and flags may be)");
+    if (d->xi == d->xi2 || d->phi == d->phi2) return fail(SMC_E_INVAL, "the gather scratch must not alias xi or phi");
+    if (int r = check_move_common(P, N, d->n_moves, d->level, prec, d->xi, d->phi, d->n_acc)) return r;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    p->capturing = true;
+    const int r = sampler_stage(p, d, prec, off, N, s);
+    p->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (r != SMC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (ec != hipSuccess) return fail(SMC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(SMC_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    smc_graph_s* gr = new smc_graph_s();
+    gr->graph = g;
+    gr->exec = ex;
+    *out = gr;
+    return SMC_OK;
 }
 
 extern "C" int smc_pcnl_move(smc_problem p, int64_t N, double beta, double tau, int32_t n_moves, uint64_t seed,

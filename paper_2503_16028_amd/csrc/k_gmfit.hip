@@ -25,6 +25,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "stage_graph.hpp"
 
 namespace smc {
 
@@ -157,12 +158,14 @@ __global__ __launch_bounds__(256) void kmpp_dist_kernel(int64_t N, int K, int kr
 }
 
 // Centre m from d2 (m >= 1) or uniformly (m = 0); one workgroup of 1024 threads.
+// The counter is ctr, or *ctr_dev + ctr when ctr_dev is given (a stage replayed from a graph).
 __global__ __launch_bounds__(1024) void kmpp_pick_kernel(int64_t N, int m, uint64_t seed, uint64_t ctr,
-                                                         const double* __restrict__ d2, int32_t* centers) {
+                                                         const uint64_t* ctr_dev, const double* __restrict__ d2,
+                                                         int32_t* centers) {
     __shared__ double red_d[16];
     __shared__ unsigned long long red_q[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t u = kmpp_u53(seed, ctr, m);
+    const uint64_t u = kmpp_u53(seed, ctr_dev ? *ctr_dev + ctr : ctr, m);
     if (m == 0) {
         if (tid == 0) centers[0] = (int32_t)scale53(u, (uint64_t)N);
         return;
@@ -432,15 +435,16 @@ static size_t em_smem_bytes() {
 
 int64_t em_blocks(int64_t N) { return (N + EM_P - 1) / EM_P; }
 
-hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
-                         double var_floor, uint64_t seed, uint64_t ctr, const FitWorkspace& w, int32_t* centers,
-                         double* logw, double* mean, double* scale, hipStream_t s) {
+namespace {
+hipError_t gm_fit(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                  double var_floor, uint64_t seed, uint64_t ctr, const uint64_t* ctr_dev, const FitWorkspace& w,
+                  int32_t* centers, double* logw, double* mean, double* scale, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     const unsigned B = (unsigned)em_blocks(N);
-    kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, 0, seed, ctr, w.d2, centers);
+    kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, 0, seed, ctr, ctr_dev, w.d2, centers);
     for (int m = 1; m < M; ++m) {
         kmpp_dist_kernel<<<B, 256, 0, s>>>(N, K, kr, active, xi, centers, m, w.d2);
-        kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, m, seed, ctr, w.d2, centers);
+        kmpp_pick_kernel<<<1, 1024, 0, s>>>(N, m, seed, ctr, ctr_dev, w.d2, centers);
     }
     gm_colstats_kernel<<<B, 256, 0, s>>>(N, K, kr, active, xi, centers, w.part);
     gm_start_kernel<<<1, 256, 0, s>>>(N, K, kr, active, xi, centers, M, var_floor, (int)B, w.part, w.par);
@@ -458,6 +462,20 @@ hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const 
     }
     gm_output_kernel<<<1, 256, 0, s>>>(M, kr, w.par + (iters & 1) * GM_PAR, logw, mean, scale);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_gm_fit(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                         double var_floor, uint64_t seed, uint64_t ctr, const FitWorkspace& w, int32_t* centers,
+                         double* logw, double* mean, double* scale, hipStream_t s) {
+    return gm_fit(N, K, kr, active, xi, M, iters, var_floor, seed, ctr, nullptr, w, centers, logw, mean, scale, s);
+}
+
+hipError_t launch_gm_fit_ctr(int64_t N, int K, int kr, const int32_t* active, const double* xi, int M, int iters,
+                             double var_floor, uint64_t seed, const uint64_t* ctr, uint64_t ctr_off,
+                             const FitWorkspace& w, int32_t* centers, double* logw, double* mean, double* scale,
+                             hipStream_t s) {
+    return gm_fit(N, K, kr, active, xi, M, iters, var_floor, seed, ctr_off, ctr, w, centers, logw, mean, scale, s);
 }
 
 // ------------------------------------------------------------------ fit without allocation

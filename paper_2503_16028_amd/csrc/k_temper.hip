@@ -2,6 +2,7 @@
 // Both run in one workgroup: the work is a few dozen reductions over N values, so the cost
 // is latency, and a single workgroup keeps every reduction in one fixed order.
 #include "common.hpp"
+#include "stage_graph.hpp"
 
 namespace smc {
 
@@ -209,11 +210,18 @@ __device__ __forceinline__ int64_t first_output(uint64_t C, int64_t N, uint64_t 
     return q + ((r << 53) > (unsigned __int128)u53 * Q ? 1 : 0);
 }
 
+// With ctr_dev the uniform is drawn here, as smc_philox_u53(seed, *ctr_dev + ctr_off) draws it on
+// the host: the first two words of the counter block RESAMPLE_BLOCK, 27 + 26 bits.
 __global__ __launch_bounds__(TB) void resample_kernel(int64_t N, const double* __restrict__ W, uint64_t u53,
+                                                      uint64_t seed, const uint64_t* ctr_dev, uint64_t ctr_off,
                                                       int32_t* __restrict__ idx, int32_t* __restrict__ flags) {
     __shared__ uint64_t part[TB];
     __shared__ int bad;
     const int tid = threadIdx.x;
+    if (ctr_dev) {
+        const uint4 w = draw(seed, *ctr_dev + ctr_off, RESAMPLE_BLOCK, 0u);
+        u53 = ((uint64_t)(w.x >> 5) << 26) | (uint64_t)(w.y >> 6);
+    }
     if (tid == 0) bad = 0;
     __syncthreads();
     const int64_t per = (N + TB - 1) / TB;
@@ -254,7 +262,63 @@ __global__ __launch_bounds__(TB) void resample_kernel(int64_t N, const double* _
 }
 
 hipError_t launch_resample(int64_t N, const double* W, uint64_t u53, int32_t* idx, int32_t* flags, hipStream_t s) {
-    resample_kernel<<<dim3(1), dim3(TB), 0, s>>>(N, W, u53, idx, flags);
+    resample_kernel<<<dim3(1), dim3(TB), 0, s>>>(N, W, u53, 0, nullptr, 0, idx, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_ctr(int64_t N, const double* W, uint64_t seed, const uint64_t* ctr, uint64_t ctr_off,
+                               int32_t* idx, int32_t* flags, hipStream_t s) {
+    resample_kernel<<<dim3(1), dim3(TB), 0, s>>>(N, W, 0, seed, ctr, ctr_off, idx, flags);
+    return hipGetLastError();
+}
+
+// End of a tempering stage for G samplers, one workgroup: for every group still running (its first
+// row not parked; always, without a level map) the acceptance rate of its moves (an integer sum),
+// a record of the stage (tau, h, the beta the moves used, the rate, the log-evidence increment) at
+// row ctr / stride - 1, then the step-size rule (double beta above a rate of 0.3, halve it below
+// 0.15, at most 1), and a group whose temperature has reached 1 parks its rows.  Last, the counter
+// moves to the next stage.
+__global__ __launch_bounds__(TB) void stage_rule_kernel(StageRule r) {
+    __shared__ unsigned long long part[TB];
+    const int tid = threadIdx.x;
+    const uint64_t c = *r.ctr;
+    const int64_t row = (int64_t)(c / r.stride) - 1;
+    for (int g = 0; g < r.G; ++g) {
+        const int64_t off = r.off[g], n = r.count[g];
+        const bool running = !r.level || r.level[off] != SMC_LEVEL_PARKED;   // uniform
+        if (!running) continue;
+        unsigned long long a = 0;
+        for (int64_t k = tid; k < n; k += TB) a += (unsigned long long)r.n_acc[off + k];
+        part[tid] = a;
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if (tid < w) part[tid] += part[tid + w];
+            __syncthreads();
+        }
+        const unsigned long long acc = part[0];
+        __syncthreads();
+        const double beta = r.beta[g], tau = r.tau[g];
+        if (tid == 0) {
+            const double rate = (double)acc / ((double)n * (double)(r.n_moves > 1 ? r.n_moves : 1));
+            if (row >= 0 && row < r.max_stages) {
+                double* rec = r.record + ((size_t)row * r.G + g) * 5;
+                rec[0] = tau;
+                rec[1] = r.h[g];
+                rec[2] = beta;
+                rec[3] = rate;
+                rec[4] = r.log_z[g];
+            }
+            r.beta[g] = rate > 0.3 ? fmin(1.0, 2.0 * beta) : (rate < 0.15 ? 0.5 * beta : beta);
+        }
+        if (r.level && tau >= 1.0)
+            for (int64_t k = tid; k < n; k += TB) r.level[off + k] = SMC_LEVEL_PARKED;
+        __syncthreads();
+    }
+    if (tid == 0) *r.ctr = c + r.stride;
+}
+
+hipError_t launch_stage_rule(const StageRule& r, hipStream_t s) {
+    stage_rule_kernel<<<dim3(1), dim3(TB), 0, s>>>(r);
     return hipGetLastError();
 }
 

@@ -10,7 +10,9 @@ SMC-pCN-GM, per stage, in the order S^N P_{j+1} L_{j+1} of Sec. 2.2 (eq. (decide
 SMC-GM replaces the moves by smc_gm_draw: every particle becomes an independent draw from the
 fitted mixture, accepted without a test, and its potential is what the next stage re-weights.
 Both loops end when the cumulative temperature reaches 1.  Every step runs on the device; the
-host reads back the temperature (and the acceptance count) once per stage.  Random numbers:
+host reads back the temperature (and the acceptance count) once per stage.  With graph=True the
+whole SMC-pCN-GM stage (every call above and the step-size rule) is one captured graph
+(smc_sampler_graph_create) replayed once per stage, with the same bits as the calls one by one.  Random numbers:
 stage s draws its resampling uniform from Philox block 0x80000001 and its moves, mixture fit and
 mixture draws at counters s * 2^20 (+ move index), so a run is a function of its seed alone.
 """
@@ -42,7 +44,9 @@ def pcn_mixture(kr, device):
 
 class SMCSampler:
     def __init__(self, problem, N, M, n_moves, ess_frac=0.5, beta0=0.2, prec=smc.SMC_FP32_REFINE, seed=0,
-                 device="cuda", fit_iters=50):
+                 device="cuda", fit_iters=50, graph=False):
+        self.graph = bool(graph)
+        self._sg = None
         self.p, self.N, self.M, self.n_moves = problem, int(N), int(M), int(n_moves)
         self.fit_iters = int(fit_iters)
         self.ess_frac, self.beta, self.prec, self.seed = ess_frac, float(beta0), prec, int(seed)
@@ -79,6 +83,8 @@ class SMCSampler:
 
     def step(self):
         """One stage: temper, resample, gather, mixture, moves, step-size rule."""
+        if self.graph:
+            raise RuntimeError("a sampler built with graph=True runs its stages through run()")
         p, N = self.p, self.N
         self.stage += 1
         base = self.stage * STAGE_STRIDE
@@ -113,6 +119,8 @@ class SMCSampler:
         """Run to temperature 1 (at most max_stages stages in all).  A sampler restored with
         load_state_dict continues where the saved one stopped; stop_after ends this call after that
         many stages (for a checkpoint) with the sampler still below temperature 1."""
+        if self.graph:
+            return self._run_graph(max_stages, stop_after)
         if self.stage == 0:
             self.initialise()
         done = 0
@@ -121,6 +129,60 @@ class SMCSampler:
                 break
             self.step()
             done += 1
+        if int(self.flags.item()) & smc.FLAG_STALL:
+            raise RuntimeError("temperature bisection stalled")
+        return dict(xi=self.xi, phi=self.phi, log_Z=self.log_Z, history=self.history)
+
+    GRAPH_RECORD = 1024   # stages a graph-driven run can record
+
+    def _stage_graph(self):
+        """The whole-stage graph over this sampler's tensors (built once, on its own stream)."""
+        if self._sg is None:
+            dev, M, kr = self.dev, self.M, self.p.kr
+            f64 = dict(dtype=torch.float64, device=dev)
+            self._gstream = torch.cuda.Stream(device=dev)
+            logw, mean, scale = pcn_mixture(kr, dev) if M == 1 else (torch.zeros(M, **f64),
+                                                                    torch.zeros(M, kr, **f64),
+                                                                    torch.ones(M, kr, **f64))
+            self._gt = dict(xi=self.xi, phi=self.phi, xi2=self.xi2, phi2=self.phi2, W=self.W, idx=self.idx,
+                            tau=self.tau, tau_new=self.tau_new, h=self.h, log_z=self.log_z,
+                            beta=torch.full((1,), self.beta, **f64), logw=logw.reshape(1, M),
+                            mean=mean.reshape(1, M, kr), scale=scale.reshape(1, M, kr),
+                            ctr=torch.zeros(1, dtype=torch.int64, device=dev), n_acc=self.n_acc,
+                            record=torch.full((self.GRAPH_RECORD, 1, 5), math.nan, **f64), flags=self.flags)
+            torch.cuda.synchronize(dev)
+            self._sg = smc.SamplerGraph(self.p, [self.N], M, self.n_moves, self.fit_iters, self.ess_frac, 1e-3,
+                                        self.seed, STAGE_STRIDE, self.prec, self._gt, self._gstream,
+                                        self.GRAPH_RECORD)
+        return self._sg
+
+    def _run_graph(self, max_stages, stop_after):
+        if max_stages > self.GRAPH_RECORD:
+            raise ValueError("a graph-driven run records at most %d stages" % self.GRAPH_RECORD)
+        if self.stage == 0:
+            self.initialise()
+        g = self._stage_graph()
+        t = self._gt
+        first = self.stage
+        torch.cuda.synchronize(self.dev)
+        with torch.cuda.stream(self._gstream):
+            t["ctr"].fill_((self.stage + 1) * STAGE_STRIDE)   # stage s runs at counter s * 2^20
+            t["beta"].fill_(self.beta)
+            done = 0
+            while float(self.tau.item()) < 1.0 and self.stage < max_stages:
+                if stop_after is not None and done >= stop_after:
+                    break
+                g.launch(self._gstream)
+                self.stage += 1
+                done += 1
+                self._check_step(float(self.tau.item()))
+            rec = t["record"][:, 0].cpu()
+            self.beta = float(t["beta"].item())
+        for s in range(first, self.stage):
+            tau, h, beta, rate, lz = (float(v) for v in rec[s])
+            self.log_Z += lz
+            self.history.append(dict(stage=s + 1, tau=tau, h=h, beta=beta, rate=rate))
+        torch.cuda.synchronize(self.dev)
         if int(self.flags.item()) & smc.FLAG_STALL:
             raise RuntimeError("temperature bisection stalled")
         return dict(xi=self.xi, phi=self.phi, log_Z=self.log_Z, history=self.history)
@@ -205,6 +267,9 @@ class MixedSampler:
 
     def __init__(self, problem, counts, M, n_moves, ess_frac=0.5, beta0=0.2, prec=smc.SMC_FP32_REFINE, seed=0,
                  device="cuda", fit_iters=50, graph=True):
+        """graph: True captures the move stage (smc_stage_graph_create) and runs tempering,
+        resampling and the fits as separate calls; "stage" captures the whole stage of every
+        sampler (smc_sampler_graph_create), so a stage is one launch; False makes every call."""
         G = len(counts)
         if G != len(problem.grids):
             raise ValueError("one sampler per grid of the problem (%d), got %d" % (len(problem.grids), G))
@@ -242,7 +307,9 @@ class MixedSampler:
         self.sd = smc.stage_desc(G, self.logw, self.mean, self.scale, self.beta, self.tau, self.ctr, self.seed)
         self.stream.synchronize()
         self.graph = None
-        if graph:
+        self.whole = graph == "stage"
+        self.sg = None
+        if graph and not self.whole:
             self.graph = smc.StageGraph(problem, N, self.level, self.sd, self.n_moves, prec, self.xi, self.phi,
                                         self.n_acc, self.stream)
         self.stage = 0
@@ -258,8 +325,56 @@ class MixedSampler:
             smc.smc_prior_sample(self.p, self.N, self.seed, 0, self.xi)
             smc.smc_phi_batch(self.p, self.N, self.xi, self.level, self.prec, self.phi)
 
+    GRAPH_RECORD = 1024   # stages a whole-stage graph records
+
+    def _whole_graph(self):
+        if self.sg is None:
+            G = len(self.counts)
+            f64 = dict(dtype=torch.float64, device=self.xi.device)
+            with torch.cuda.stream(self.stream):
+                self.record = torch.full((self.GRAPH_RECORD, G, 5), math.nan, **f64)
+            self.stream.synchronize()
+            t = dict(xi=self.xi, phi=self.phi, xi2=self.xi2, phi2=self.phi2, W=self.W, idx=self.idx, tau=self.tau,
+                     tau_new=self.tau_new, h=self.h, log_z=self.log_z, beta=self.beta, logw=self.logw,
+                     mean=self.mean, scale=self.scale, ctr=self.ctr, level=self.level, n_acc=self.n_acc,
+                     record=self.record, flags=self.flags)
+            self.sg = smc.SamplerGraph(self.p, self.counts, self.M, self.n_moves, self.fit_iters, self.ess_frac,
+                                       1e-3, self.seed, STAGE_STRIDE, self.prec, t, self.stream, self.GRAPH_RECORD)
+        return self.sg
+
+    def _step_whole(self):
+        """One stage of every sampler as one launch of the whole-stage graph; the host reads the
+        temperatures to stop and to catch a stalled step."""
+        g = self._whole_graph()
+        self.stage += 1
+        with torch.cuda.stream(self.stream):
+            if self.stage == 1:
+                self.ctr.fill_(STAGE_STRIDE)
+                self.beta.copy_(torch.tensor(self.betas, dtype=torch.float64))
+            g.launch(self.stream)
+            taus = self.tau.cpu().numpy()
+            hs = self.h.cpu().numpy()
+        for k in self.running:
+            if taus[k] < 1.0 and hs[k] == 0.0:
+                raise RuntimeError("temperature bisection of sampler %d stalled at stage %d" % (k, self.stage))
+        self.running = [k for k in self.running if taus[k] < 1.0]
+        return len(self.running)
+
+    def _collect_whole(self):
+        rec = self.record.cpu().numpy()
+        for g in range(len(self.counts)):
+            for s in range(self.stage):
+                tau, h, beta, rate, lz = (float(v) for v in rec[s, g])
+                if math.isnan(tau):
+                    continue
+                self.log_Z[g] += lz
+                self.history[g].append(dict(stage=s + 1, tau=tau, h=h, beta=beta, rate=rate))
+        self.betas = [float(b) for b in self.beta.cpu().numpy()]
+
     def step(self):
         """One stage of every running sampler: temper, resample, gather, fit; then one move stage."""
+        if self.whole:
+            return self._step_whole()
         p, K = self.p, self.p.K
         self.stage += 1
         base = self.stage * STAGE_STRIDE
@@ -307,11 +422,15 @@ class MixedSampler:
         return len(self.running)
 
     def run(self, max_stages=500):
+        if self.whole and max_stages > self.GRAPH_RECORD:
+            raise ValueError("a whole-stage graph records at most %d stages" % self.GRAPH_RECORD)
         self.initialise()
         for _ in range(max_stages):
             if self.step() == 0:
                 break
         self.stream.synchronize()
+        if self.whole:
+            self._collect_whole()
         if int(self.flags.item()) & smc.FLAG_STALL:
             raise RuntimeError("temperature bisection stalled")
         return [dict(xi=self.xi[self.rows(g)], phi=self.phi[self.rows(g)], log_Z=self.log_Z[g],
@@ -321,3 +440,6 @@ class MixedSampler:
         if self.graph is not None:
             self.graph.close()
             self.graph = None
+        if self.sg is not None:
+            self.sg.close()
+            self.sg = None

@@ -53,6 +53,16 @@ class StageDesc(ctypes.Structure):
                 ("beta", c_vp), ("tau", c_vp), ("ctr", c_vp), ("seed", c_u64)]
 
 
+class SamplerGraphDesc(ctypes.Structure):
+    _fields_ = [("n_groups", c_i32), ("counts", c_i64 * 4), ("M", c_i32), ("kr", c_i32), ("fit_iters", c_i32),
+                ("n_moves", c_i32), ("max_stages", c_i32), ("ess_frac", c_dbl), ("var_floor", c_dbl),
+                ("seed", c_u64), ("stride", c_u64),
+                ("xi", c_vp), ("phi", c_vp), ("xi2", c_vp), ("phi2", c_vp), ("W", c_vp), ("idx", c_vp),
+                ("tau", c_vp), ("tau_new", c_vp), ("h", c_vp), ("log_z", c_vp), ("beta", c_vp),
+                ("logw", c_vp), ("mean", c_vp), ("scale", c_vp), ("ctr", c_vp), ("level", c_vp), ("n_acc", c_vp),
+                ("record", c_vp), ("flags", c_vp)]
+
+
 _SIGS = {
     "smc_problem_create": (c_i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(c_vp)]),
     "smc_problem_create_l2mix": (c_i32, [ctypes.POINTER(L2MixDesc), ctypes.POINTER(c_vp)]),
@@ -80,6 +90,7 @@ _SIGS = {
     "smc_gmpcn_stage": (c_i32, [c_vp, c_i64, c_vp, ctypes.POINTER(StageDesc), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "smc_stage_graph_create": (c_i32, [c_vp, c_i64, c_vp, ctypes.POINTER(StageDesc), c_i32, c_i32, c_vp, c_vp, c_vp,
                                        c_vp, ctypes.POINTER(c_vp)]),
+    "smc_sampler_graph_create": (c_i32, [c_vp, ctypes.POINTER(SamplerGraphDesc), c_i32, c_vp, ctypes.POINTER(c_vp)]),
     "smc_stage_graph_launch": (c_i32, [c_vp, c_vp]),
     "smc_stage_graph_destroy": (None, [c_vp]),
     "smc_tile_candidates": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
@@ -386,6 +397,62 @@ class StageGraph:
                                             _ptr(xi, torch.float64, N * problem.K, "xi"),
                                             _ptr(phi, torch.float64, N, "phi"), _ptr(n_acc, torch.int32, N, "n_acc"),
                                             _stream(stream), ctypes.byref(self.handle)))
+
+    def launch(self, stream=None):
+        _check(lib().smc_stage_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().smc_stage_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SamplerGraph:
+    """A whole tempering stage of G samplers (smc_sampler_graph_create) captured once; launch()
+    runs the next stage.  The tensors are the samplers' device state, read and written in place:
+    xi [N][K], phi [N], xi2 [N][K], phi2 [N], W [N], idx [N] (int32), tau, tau_new, h, log_z and
+    beta [G], logw [G][M], mean and scale [G][M][kr], ctr [1] (int64; stage s runs at s * stride),
+    level [N] (int32, or None for one group), n_acc [N] (int32), record [max_stages][G][5], flags
+    [1] (int32, or None)."""
+
+    def __init__(self, problem, counts, M, n_moves, fit_iters, ess_frac, var_floor, seed, stride, prec, t, stream,
+                 max_stages):
+        G = len(counts)
+        N = sum(int(c) for c in counts)
+        K, kr = problem.K, problem.kr
+        d = SamplerGraphDesc()
+        d.n_groups, d.M, d.kr, d.fit_iters = G, int(M), kr, int(fit_iters)
+        for g, c in enumerate(counts):
+            d.counts[g] = int(c)
+        d.n_moves, d.max_stages = int(n_moves), int(max_stages)
+        d.ess_frac, d.var_floor, d.seed, d.stride = float(ess_frac), float(var_floor), int(seed), int(stride)
+        d.xi = _ptr(t["xi"], torch.float64, N * K, "xi")
+        d.phi = _ptr(t["phi"], torch.float64, N, "phi")
+        d.xi2 = _ptr(t["xi2"], torch.float64, N * K, "xi2")
+        d.phi2 = _ptr(t["phi2"], torch.float64, N, "phi2")
+        d.W = _ptr(t["W"], torch.float64, N, "W")
+        d.idx = _ptr(t["idx"], torch.int32, N, "idx")
+        for name in ("tau", "tau_new", "h", "log_z", "beta"):
+            setattr(d, name, _ptr(t[name], torch.float64, G, name))
+        d.logw = _ptr(t["logw"], torch.float64, G * M, "logw")
+        d.mean = _ptr(t["mean"], torch.float64, G * M * kr, "mean")
+        d.scale = _ptr(t["scale"], torch.float64, G * M * kr, "scale")
+        d.ctr = _ptr(t["ctr"], torch.int64, 1, "ctr")
+        d.level = _ptr(t.get("level"), torch.int32, N, "level", optional=True)
+        d.n_acc = _ptr(t["n_acc"], torch.int32, N, "n_acc")
+        d.record = _ptr(t["record"], torch.float64, max_stages * G * 5, "record")
+        d.flags = _ptr(t.get("flags"), torch.int32, 1, "flags", optional=True)
+        self.handle = c_vp()
+        # the graph holds device addresses: keep every tensor alive as long as it exists
+        self._keep = (problem, dict(t), d)
+        _check(lib().smc_sampler_graph_create(problem.handle, ctypes.byref(d), prec, _stream(stream),
+                                              ctypes.byref(self.handle)))
 
     def launch(self, stream=None):
         _check(lib().smc_stage_graph_launch(self.handle, _stream(stream)))
