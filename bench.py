@@ -276,6 +276,47 @@ def mixed_variant(dev, counts=(4096, 3072, 1024), n_moves=20, stages=2):
             "mixed_counts": list(counts)}
 
 
+def stage_graph_variant(dev, N=4096, M=8, n_moves=20, counts=(4096, 3072, 1024), mixed_stages=3):
+    """Whole SMC-pCN-GM runs (every stage: tempering, resampling, gather, mixture fit, moves, step
+    rule) made call by call and as one captured graph per stage; the same bits either way."""
+    import torch
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import MixedSampler, SMCSampler
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_c3.json")))
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    out, runs = {}, []
+    for graph in (False, True):
+        s = SMCSampler(p, N, M, n_moves, seed=2503, graph=graph, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        runs.append(s)
+        key = "graph" if graph else "calls"
+        out["c3_run_%s_s" % key] = dt
+        out["c3_stage_%s_ms" % key] = 1e3 * dt / max(1, s.stage)
+    out["c3_run_stages"] = runs[0].stage
+    out["c3_graph_same_bits"] = bool(torch.equal(runs[0].xi, runs[1].xi) and runs[0].log_Z == runs[1].log_Z)
+    p.close()
+    d5 = json.load(open(os.path.join(ROOT, "tests", "golden", "problem_c5.json")))
+    p5 = smc.Problem(d5, sum(counts), tol64=1e-10, tol_inner=1e-3)
+    for graph in (True, "stage"):
+        ms = MixedSampler(p5, counts, M, n_moves, seed=2503, graph=graph, device=dev)
+        ms.initialise()
+        ms.stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(mixed_stages):
+            ms.step()
+        ms.stream.synchronize()
+        dt = time.perf_counter() - t0
+        key = "whole_graph" if graph == "stage" else "moves_graph"
+        out["mixed_stage_%s_ms" % key] = 1e3 * dt / mixed_stages
+        ms.close()
+    p5.close()
+    return out
+
+
 SOLVE_ONLY = {
     # name: (problem, grids, particles per grid, precision)
     "c3_fp32": ("c3", [128], [4096], 1),
@@ -440,6 +481,7 @@ def main():
         variants.update(example1_variant(dev))
         variants.update(mixed_variant(dev))
         variants.update(runs_variant(dev))
+        variants.update(stage_graph_variant(dev))
         # FP64 conjugate gradients with the same preconditioner, on the headline's protocol: the same
         # seed, stages, warm-up and moves per stage, so the ratio compares precisions alone
         t64, prof64, _ = stage_loop(smc.SMC_FP64, args.steps, args.warmup, args.moves)

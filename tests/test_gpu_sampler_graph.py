@@ -119,6 +119,7 @@ def test_mixed_whole_stage_graph_gives_the_bits_of_the_calls():
         out = [dict(xi=ms.xi[ms.rows(g)].cpu().numpy(), phi=ms.phi[ms.rows(g)].cpu().numpy(), log_Z=ms.log_Z[g],
                     history=ms.history[g], end=ends[g]) for g in range(3)]
         assert int(ms.flags.item()) == 0
+        banner("graph", graph, "stages at which the samplers reached 1:", [ends[g] for g in range(3)])
         ms.close()
         for g in range(3):
             assert out[g]["history"][-1]["tau"] == 1.0
@@ -129,4 +130,5 @@ def test_mixed_whole_stage_graph_gives_the_bits_of_the_calls():
         assert np.array_equal(a["xi"], b["xi"]) and np.array_equal(a["phi"], b["phi"])
         assert a["log_Z"] == b["log_Z"] and a["end"] == b["end"]
         assert a["history"] == b["history"]
+    assert len({res[1][g]["end"] for g in range(3)}) > 1   # some sampler went on after another finished
     p.close()
