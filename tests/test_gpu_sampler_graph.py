@@ -132,3 +132,44 @@ def test_mixed_whole_stage_graph_gives_the_bits_of_the_calls():
         assert a["history"] == b["history"]
     assert len({res[1][g]["end"] for g in range(3)}) > 1   # some sampler went on after another finished
     p.close()
+
+
+def test_sampler_graph_rejects_bad_arguments():
+    """Invalid descriptions fail with SMC_E_INVAL before any capture, leaving the stream usable."""
+    from paper_2503_16028_amd import smc
+    banner("sampler graph argument checks")
+    d = load("t2")
+    N, M = 64, 3
+    p = smc.Problem(d, N, grids=[32])
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    K, kr = p.K, p.kr
+    R, G3, MM = N + 8, 3, 100   # room for every bad shape below, so that only the library objects
+    t = dict(xi=torch.zeros(R, K, **f64), phi=torch.zeros(R, **f64), xi2=torch.zeros(R, K, **f64),
+             phi2=torch.zeros(R, **f64), W=torch.zeros(R, **f64), idx=torch.zeros(R, dtype=torch.int32, device=dev),
+             tau=torch.zeros(G3, **f64), tau_new=torch.zeros(G3, **f64), h=torch.zeros(G3, **f64),
+             log_z=torch.zeros(G3, **f64), beta=torch.full((G3,), 0.2, **f64), logw=torch.zeros(G3, MM, **f64),
+             mean=torch.zeros(G3, MM, kr, **f64), scale=torch.ones(G3, MM, kr, **f64),
+             ctr=torch.zeros(1, dtype=torch.int64, device=dev), n_acc=torch.zeros(R, dtype=torch.int32, device=dev),
+             record=torch.zeros(4, G3, 5, **f64))
+    s = torch.cuda.Stream()
+
+    def make(counts=(N,), M_=M, stride=1 << 20, **over):
+        tt = dict(t, **over)
+        return smc.SamplerGraph(p, list(counts), M_, 2, 10, 0.5, 1e-3, 1, stride, smc.SMC_FP64, tt, s, 4)
+
+    bad = [dict(counts=(N // 2, N // 2)),            # two groups without a level map
+           dict(counts=(0,)),                        # an empty group
+           dict(counts=(N + 1,)),                    # more rows than the problem holds
+           dict(M_=0), dict(M_=99),                  # mixture size
+           dict(stride=0),                           # counter spacing
+           dict(xi2=t["xi"]),                        # gather scratch aliasing the particles
+           dict(level=torch.zeros(R, dtype=torch.int32, device=dev))]   # a level map on a one-grid 32^2 problem
+    for kw in bad:
+        with pytest.raises(smc.SMCError) as e:
+            make(**kw)
+        assert e.value.status == smc.SMC_E_INVAL, kw
+    g = make()                                       # the stream still captures a valid stage
+    g.close()
+    s.synchronize()
+    p.close()
