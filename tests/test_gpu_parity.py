@@ -58,8 +58,8 @@ def _lib():
 
 # ------------------------------------------------------------------ synthesis and draws
 
-@pytest.mark.parametrize("name,grid,N", [("t2", 16, 5), ("t2", 64, 3), ("c3", 128, 3), ("c5", 256, 2),
-                                         ("t1", 64, 4), ("c1", 64, 3)])
+@pytest.mark.parametrize("name,grid,N", [("t2", 16, 5), ("t2", 32, 4), ("t2", 64, 3), ("c2", 64, 3), ("c3", 128, 3),
+                                         ("c5", 256, 2), ("t1", 64, 4), ("c1", 64, 3)])
 def test_synthesis(name, grid, N):
     from paper_2503_16028_amd import smc
     banner("synthesis", name, grid, N)
