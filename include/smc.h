@@ -247,7 +247,9 @@ void smc_stage_graph_destroy(smc_graph g);
  * pCN-GM moves of all groups (as smc_gmpcn_stage); then a rule on the device that records the
  * stage, adapts each group's step size and parks a group that has reached temperature 1.
  * Every per-stage value lives in device memory, so each smc_stage_graph_launch runs the next
- * stage with no host work; the host reads tau to stop (or parks nothing and stops by itself).
+ * stage with no host work between launches; the caller reads tau after a launch to decide whether
+ * to launch again (with a level map, a stage launched after every group has reached 1 changes no
+ * row; without one, its moves still run, at temperature 1).
  * Group g owns the rows [off_g, off_g + counts[g]), off_g = counts[0] + ... + counts[g-1]; with
  * a level map (G = the problem's n_levels, level[row] = g at the start) group g solves on grid g,
  * without one (G = 1) every row is group 0.  Random numbers: stage s (s = *ctr / stride) moves
@@ -263,7 +265,10 @@ void smc_stage_graph_destroy(smc_graph g);
  * SMC_LEVEL_PARKED.  Then *ctr += stride.
  * All arrays are device arrays that stay valid while the graph exists; the graph reads and
  * writes them in place and uses the problem's workspace (launches must not overlap other calls
- * on the problem).  For callers that replay stages without host work between them. */
+ * on the problem).  Errors: SMC_E_INVAL (nothing captured) for a NULL array other than level,
+ * flags and (max_stages = 0) record, G or counts out of range, more rows than n_max, M outside
+ * 1..16, kr unlike the problem's, stride 0, xi2 or phi2 aliasing xi or phi, or a level map the
+ * problem cannot mix; SMC_E_HIP if capture or instantiation fails. */
 typedef struct {
     int32_t n_groups;                /* G: 1, or the problem's n_levels with a level map */
     int64_t counts[4];               /* host: rows of each group (the first G entries) */
