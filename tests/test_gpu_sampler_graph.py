@@ -173,3 +173,25 @@ def test_sampler_graph_rejects_bad_arguments():
     g.close()
     s.synchronize()
     p.close()
+
+
+def test_whole_stage_graph_at_the_metric_configuration():
+    """128^2, N = 4096, M = 8, 20 moves per stage, FP32 with refinement at the benchmark's
+    tolerances: three stages as graph launches give the bits of three call-by-call stages."""
+    from paper_2503_16028_amd import smc
+    from paper_2503_16028_amd.sampler import SMCSampler
+    banner("sampler graph metric configuration")
+    d = load("c3")
+    N, M, n_moves = 4096, 8, 20
+    p = smc.Problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    runs = []
+    for graph in (False, True):
+        s = SMCSampler(p, N, M, n_moves, seed=2503, graph=graph)
+        s.run(stop_after=3)
+        torch.cuda.synchronize()
+        runs.append(s)
+    a, b = runs
+    assert a.stage == 3
+    same_run(a, b, a.history, b.history)
+    assert all(0.0 < h["rate"] <= 1.0 for h in a.history)
+    p.close()
