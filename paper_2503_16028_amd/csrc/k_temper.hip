@@ -314,6 +314,7 @@ __global__ __launch_bounds__(TB) void stage_rule_kernel(StageRule r) {
             for (int64_t k = tid; k < n; k += TB) r.level[off + k] = SMC_LEVEL_PARKED;
         __syncthreads();
     }
+    __syncthreads();   // every thread has read the counter (the loop may have had no barrier)
     if (tid == 0) *r.ctr = c + r.stride;
 }
 
