@@ -81,6 +81,26 @@ def test_value_and_grad_fp64(name, grid, N):
     assert smc.smc_status_flags(p) == 0
 
 
+@pytest.mark.parametrize("kl,grid", [(5, 64), (31, 32)])
+def test_value_and_grad_odd_mode_counts(kl, grid):
+    """The gradient's contraction with mode counts other than 32 (the even/odd split of its first
+    product and the masked output), FP64, against the oracle's adjoint gradient."""
+    from paper_2503_16028_amd import smc
+    banner("value_and_grad kl", kl, grid)
+    d, _ = load("t2")
+    d = dict(d, kl_per_axis=kl, kr=min(12, kl * kl))
+    op = OProblem(d)
+    N = 2
+    p = fp64_problem(d, N, grid)
+    xi = inputs.particles(N, op.K, 23)
+    phi, g, it = gpu_value_and_grad(p, t(xi), smc.SMC_FP64)
+    assert (it > 0).all(), it
+    for k in range(N):
+        rphi, rg = value_and_grad(op, xi[k], grid)
+        assert abs(phi[k] / rphi - 1) <= 1e-10
+        assert np.abs(g[k] - rg).max() <= 1e-10 * np.abs(rg).max()
+
+
 @pytest.mark.parametrize("name,grid,N", [("t2", 32, 4), ("t2", 64, 3), ("c4", 128, 3)])
 def test_value_and_grad_fp32_refine(name, grid, N):
     from paper_2503_16028_amd import smc

@@ -76,6 +76,27 @@ def test_synthesis(name, grid, N):
         assert np.abs(got[k] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("kl,grid", [(1, 16), (5, 32), (31, 64), (17, 128)])
+def test_synthesis_odd_mode_counts(kl, grid):
+    """Mode counts other than the padded 32 (odd ones included): the even/odd split of the
+    products and the zero padding of the coefficient tile, against the oracle's synthesis."""
+    from paper_2503_16028_amd import smc
+    banner("synthesis kl", kl, grid)
+    d, _ = load("t2")
+    d = dict(d, kl_per_axis=kl, kr=min(12, kl * kl))
+    op = OProblem(d)
+    N = 3
+    p = gpu_problem(d, N, grids=[grid])
+    xi = inputs.particles(N, op.K, 7)
+    u = torch.empty(N, (grid + 1) ** 2, dtype=torch.float64, device=DEV)
+    smc.smc_synthesize(p, N, t(xi), 0, u)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    for k in range(N):
+        ref = synthesize(op, xi[k], grid).T.reshape(-1)
+        assert np.abs(got[k] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
 def test_prior_sample_matches_generator():
     from paper_2503_16028_amd import smc
     banner("prior sample")
