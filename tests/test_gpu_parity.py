@@ -76,6 +76,24 @@ def test_synthesis(name, grid, N):
         assert np.abs(got[k] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
 
 
+def test_synthesis_full_batch_sampled():
+    """The metric workload's launch shape (128^2, 32 x 32 modes, 4096 particles, one workgroup per
+    particle): eight particles spread over the batch against the oracle's synthesis."""
+    from paper_2503_16028_amd import smc
+    banner("synthesis full batch 128 4096")
+    d, op = load("c3")
+    N = 4096
+    p = gpu_problem(d, N)
+    xi = inputs.particles(N, op.K, 31)
+    u = torch.empty(N, 129 * 129, dtype=torch.float64, device=DEV)
+    smc.smc_synthesize(p, N, t(xi), 0, u)
+    torch.cuda.synchronize()
+    for k in (0, 1, 255, 256, 1023, 2048, 4094, 4095):
+        ref = synthesize(op, xi[k], 128).T.reshape(-1)
+        got = u[k].cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), k
+
+
 @pytest.mark.parametrize("kl,grid", [(1, 16), (5, 32), (31, 64), (17, 128)])
 def test_synthesis_odd_mode_counts(kl, grid):
     """Mode counts other than the padded 32 (odd ones included): the even/odd split of the
