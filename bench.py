@@ -395,8 +395,8 @@ def main():
                     help="also copy 256 MiB device-to-device, to calibrate memory-traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs the move stage on one GPU only (--gpus %d requested); the multi-GPU sharding "
-              "is a design, not part of this build" % args.gpus, file=sys.stderr)
+        print("bench.py runs the move stage on one GPU only (--gpus %d requested); sharding the particles "
+              "across GPUs is not implemented" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.solve_only:
         solve_only(args.solve_only, args.reps, args.copy_probe)

@@ -1,7 +1,7 @@
 """Pins of the oracle's mixture fit, mixture draw and SMC-GM loop (CPU only).
 
-The fit's estimator is the build's own stand-in (the paper's is not described), so the
-pins check that it computes what it states: the pairwise sum order of the seeding's
+The fit's estimator is a stand-in of this library (the paper's is not described), so the
+pins check that it computes what it states: the exactly rounded sums of the seeding's
 distances, the k-means++ selection probabilities, the EM step's closed form for one
 component, the monotone likelihood of EM, and recovery of a known mixture.
 """
