@@ -3,9 +3,10 @@
 // 2D: the cosine basis is separable, phi_kl(x_i, y_j) = B[i][k] B[j][l], so per particle
 //     u[j][i] = sum_k sum_l B[i][k] X[k][l] B[j][l],   X[k][l] = sqrt(lambda_kl) xi_kl,
 // i.e. two small dense products T = X B^T (32 x (n+1)) and U = T^T B^T ((n+1) x (n+1)).
-// Both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64), X and T in LDS (T written over X)
-// and B read straight into registers; the epilogue optionally returns exp(u/2), the nodal factor of the geometric-mean face
-// coefficient exp((u_P + u_Q)/2) = exp(u_P/2) exp(u_Q/2) of the forward operator.
+// Both run on the FP64 matrix cores (v_mfma_f64_16x16x4f64), X and T in LDS (T written over
+// X) and B read straight into registers; the epilogue optionally returns exp(u/2), the nodal
+// factor of the geometric-mean face coefficient exp((u_P + u_Q)/2) = exp(u_P/2) exp(u_Q/2) of the
+// forward operator.
 #include "common.hpp"
 #include "synth_body.hpp"
 

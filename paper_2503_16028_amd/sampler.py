@@ -12,8 +12,8 @@ fitted mixture, accepted without a test, and its potential is what the next stag
 Both loops end when the cumulative temperature reaches 1.  Every step runs on the device; the
 host reads back the temperature (and the acceptance count) once per stage.  With graph=True the
 whole SMC-pCN-GM stage (every call above and the step-size rule) is one captured graph
-(smc_sampler_graph_create) replayed once per stage, with the same bits as the calls one by one.  Random numbers:
-stage s draws its resampling uniform from Philox block 0x80000001 and its moves, mixture fit and
+(smc_sampler_graph_create) replayed once per stage, with the same bits as the calls one by one.
+Random numbers: stage s draws its resampling uniform from Philox block 0x80000001 and its moves, mixture fit and
 mixture draws at counters s * 2^20 (+ move index), so a run is a function of its seed alone.
 """
 import math
@@ -257,7 +257,8 @@ class MixedSampler:
     temperature, increment, step size, resampling, mixture and evidence, exactly as SMCSampler
     would run it on that grid alone.  Each stage, every sampler still below temperature 1
     re-weights, resamples and fits its mixture on its own rows; then one smc_gmpcn_stage (captured
-    once as a HIP graph) moves all of them, each move's solves one launch per grid.  A sampler whose temperature reaches 1 parks its particles (level SMC_LEVEL_PARKED):
+    once as a HIP graph) moves all of them, each move's solves one launch per grid.  A sampler
+    whose temperature reaches 1 parks its particles (level SMC_LEVEL_PARKED):
     its final cloud is kept as it is and costs nothing in later stages.
 
     Random numbers: moves at counter s * 2^20 + m, with a particle's global index as its word, so
