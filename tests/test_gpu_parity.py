@@ -524,3 +524,43 @@ def test_full_size_metric_configuration_sampled():
     assert np.array_equal(n_acc.cpu().numpy()[pick], racc)
     assert np.abs(xi.cpu().numpy()[pick] - rx).max() <= 1e-6
     assert np.abs(phi.cpu().numpy()[pick] / rphi - 1).max() <= 1e-4
+
+
+def test_batch_with_offsets_beyond_2_31_elements():
+    """128^2 with N = 131072 (about 190 GB of workspace): the node fields of particles past
+    129050 start beyond element 2^31 of their arrays (131071 x 16641 = 2.18e9), so an offset kept
+    in 32 bits anywhere on the path would wrap.  Prior draw, forward map, potential and one pCN-GM
+    move for the whole batch; particles at both ends replayed by the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("batch offsets beyond 2^31: 128^2 N=131072")
+    d, op = load("c3")
+    N = 131072
+    pick = [0, 65535, 129049, 129051, 131070, 131071]
+    assert pick[-1] * 129 * 129 > 2 ** 31
+    p = gpu_problem(d, N, tol64=1e-10, tol_inner=1e-3)
+    xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    smc.smc_prior_sample(p, N, 2503, 0, xi)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    phi = torch.empty(N, dtype=torch.float64, device=DEV)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G, it)
+    smc.smc_potential(p, N, G, phi)
+    torch.cuda.synchronize()
+    xi_h = philox.normals(2503, 0, np.array(pick), op.K)
+    assert np.abs(xi[pick].cpu().numpy() - xi_h).max() < 1e-13
+    assert (it.cpu().numpy() > 0).all()
+    ref = potential(oracle_G(op, xi_h, 128), op.y, op.sigma)
+    assert np.abs(phi[pick].cpu().numpy() / ref - 1).max() <= 1e-4
+    logw, mean, scale = inputs.mixture(8, op.kr, 43, spread=0.5)
+    n_acc = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_gmpcn_move(p, N, (t(logw), t(mean), t(scale)), 0.2, 0.05, 1, 9, 500, None, smc.SMC_FP32_REFINE, xi,
+                       phi, n_acc)
+    gm = GM(logw, mean, scale, op.active(), op.K)
+    rx, rphi, racc = gmpcn_moves(op, 128, xi_h, ref, gm, 0.2, 0.05, 1, 9, 500, ids=pick)
+    assert np.array_equal(n_acc[pick].cpu().numpy(), racc)
+    assert np.abs(xi[pick].cpu().numpy() - rx).max() <= 1e-6
+    assert np.abs(phi[pick].cpu().numpy() / rphi - 1).max() <= 1e-4
+    assert smc.smc_status_flags(p) == 0
+    del xi, G, it, phi, n_acc
+    p.close()
+    torch.cuda.empty_cache()
