@@ -564,3 +564,31 @@ def test_batch_with_offsets_beyond_2_31_elements():
     del xi, G, it, phi, n_acc
     p.close()
     torch.cuda.empty_cache()
+
+
+def test_global_solver_vectors_beyond_2_31_elements():
+    """256^2 with N = 4800: the global-memory solver's CG vectors (7 x 65536 values per particle)
+    of particles past 4681 start beyond element 2^31 of their array.  Forward map of the batch
+    (FP32 with refinement), particles at both ends against the oracle."""
+    from paper_2503_16028_amd import smc
+    banner("global solver vectors beyond 2^31: 256^2 N=4800")
+    d, op = load("c5")
+    N = 4800
+    pick = [0, 4681, 4799]
+    assert pick[-1] * 7 * 256 * 256 > 2 ** 31
+    p = gpu_problem(d, N, grids=[256], tol64=1e-10, tol_inner=1e-3)
+    xi = torch.empty(N, op.K, dtype=torch.float64, device=DEV)
+    smc.smc_prior_sample(p, N, 77, 0, xi)
+    G = torch.empty(N, op.n_obs, dtype=torch.float64, device=DEV)
+    it = torch.empty(N, dtype=torch.int32, device=DEV)
+    smc.smc_forward_batch(p, N, xi, None, smc.SMC_FP32_REFINE, G, it)
+    torch.cuda.synchronize()
+    assert (it.cpu().numpy() > 0).all()
+    xi_h = philox.normals(77, 0, np.array(pick), op.K)
+    assert np.abs(xi[pick].cpu().numpy() - xi_h).max() < 1e-13
+    ref = oracle_G(op, xi_h, 256)
+    assert np.abs(G[pick].cpu().numpy() / ref - 1).max() <= 1e-9
+    assert smc.smc_status_flags(p) == 0
+    del xi, G, it
+    p.close()
+    torch.cuda.empty_cache()
