@@ -13,6 +13,7 @@ taken on integers:
 Python integers make every step exact.
 """
 import bisect
+import itertools
 import math
 
 
@@ -33,3 +34,15 @@ def systematic(W, u53):
         p = ((i * 2 ** 53 + int(u53)) * Q) // D
         idx.append(bisect.bisect_right(C, p))      # first n with C_n > p
     return idx
+
+
+def systematic_at(W, u53, outputs):
+    """idx_i of systematic() for the listed outputs i only, by the same definition, for batches
+    too large to list whole."""
+    N = len(W)
+    C = list(itertools.accumulate(int(math.floor(float(w) * 2 ** 53)) for w in W))
+    Q = C[-1]
+    if Q <= 0:
+        raise ValueError("all weights are zero")
+    D = N * 2 ** 53
+    return [bisect.bisect_right(C, ((int(i) * 2 ** 53 + int(u53)) * Q) // D) for i in outputs]

@@ -19,7 +19,7 @@ from oracle import philox
 from oracle.forward import observe, potential, solve
 from oracle.moves import GM, gmpcn_moves, pcn_gm
 from oracle.problem import Problem as OProblem, synthesize
-from oracle.resample import systematic
+from oracle.resample import systematic, systematic_at
 from oracle.temper import temper
 
 pytestmark = pytest.mark.gpu
@@ -427,6 +427,29 @@ def test_resample_bit_exact(N, kind):
     idx = torch.empty(N, dtype=torch.int32, device=DEV)
     smc.smc_resample(N, t(W), u, idx)
     assert idx.cpu().numpy().tolist() == systematic(W, u)
+
+
+def test_resample_largest_batch():
+    """N = 2^24, the largest batch: 4096 outputs spread over the batch (the first and last
+    included) against the oracle one by one, and every particle's copy count within one of
+    N q_n / Q, the property of systematic resampling at any size."""
+    from paper_2503_16028_amd import smc
+    banner("resample 2^24")
+    N = 1 << 24
+    W = inputs.weights(N, 2024, "dirichlet")
+    u = inputs.u53(N)
+    idx = torch.empty(N, dtype=torch.int32, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    smc.smc_resample(N, t(W), u, idx, flags)
+    got = idx.cpu().numpy()
+    assert flags.item() == 0
+    outs = sorted(set(np.linspace(0, N - 1, 4096).astype(np.int64).tolist()))
+    assert got[outs].tolist() == systematic_at(W, u, outs)
+    assert np.all(np.diff(got) >= 0)
+    q = np.floor(W * 2.0 ** 53)
+    expect = N * q / q.sum()
+    counts = np.bincount(got, minlength=N)
+    assert np.all(np.abs(counts - expect) < 1.0 + 1e-6)
 
 
 @pytest.mark.parametrize("case", ["above_one", "negative", "nan", "inf", "sum_too_large", "exp_weights", "zero"])

@@ -12,7 +12,7 @@ from oracle.forward import observe, solve
 from oracle.moves import (GM, gmpcn_moves, log_accept_gmpcn, log_accept_pcnl, log_q, log_ratio_gmpcn,
                           log_ratio_pcnl, pcn_gm, pcnl_moves, propose_gmpcn)
 from oracle.problem import Problem, synthesize
-from oracle.resample import systematic
+from oracle.resample import systematic, systematic_at
 from oracle.temper import choose_h, log_ess, reweight, temper
 
 
@@ -226,6 +226,19 @@ def test_resampling_against_brute_force(kind):
         W = inputs.weights(N, seed, kind)
         u = inputs.u53(seed)
         assert systematic(W, u) == _brute(W, u)
+
+
+@pytest.mark.parametrize("kind", ["dirichlet", "sparse", "one"])
+def test_resampling_selected_outputs_against_brute_force(kind):
+    """systematic_at, the per-output form used on batches too large to list, against the brute
+    force on every output and against systematic on a subset."""
+    for N, seed in ((1, 4), (9, 5), (300, 6)):
+        W = inputs.weights(N, seed, kind)
+        u = inputs.u53(seed + 10)
+        assert systematic_at(W, u, range(N)) == _brute(W, u)
+        sub = [0, N // 3, N - 1]
+        full = systematic(W, u)
+        assert systematic_at(W, u, sub) == [full[i] for i in sub]
 
 
 def test_resampling_counts_and_order():
