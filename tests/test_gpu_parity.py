@@ -373,8 +373,11 @@ def test_move_fp32_refine():
 
 # ------------------------------------------------------------------ tempering and resampling
 
-@pytest.mark.parametrize("N,tau", [(1, 0.0), (7, 0.3), (1000, 0.0), (4096, 0.55)])
+@pytest.mark.parametrize("N,tau", [(1, 0.0), (7, 0.3), (1000, 0.0), (4096, 0.55), (8193, 0.2), (20000, 0.1),
+                                   (1 << 20, 0.0)])
 def test_temper(N, tau):
+    """Past 8192 potentials the kernel streams them from memory on every pass instead of keeping
+    them in registers: 8193, 20000 and 2^20 (the largest batch it takes) cover that path."""
     from paper_2503_16028_amd import smc
     banner("temper", N, tau)
     phi0 = inputs.potentials(N, 30 + N)
