@@ -266,7 +266,8 @@ void smc_stage_graph_destroy(smc_graph g);
  * All arrays are device arrays that stay valid while the graph exists; the graph reads and
  * writes them in place and uses the problem's workspace (launches must not overlap other calls
  * on the problem).  Errors: SMC_E_INVAL (nothing captured) for a NULL array other than level,
- * flags and (max_stages = 0) record, G or counts out of range, more rows than n_max, M outside
+ * flags and (max_stages = 0) record, G out of range, a group outside 1..2^20 rows (the tempering
+ * step's limit), more rows than n_max, M outside
  * 1..16, kr unlike the problem's, stride 0, xi2 or phi2 aliasing xi or phi, or a level map the
  * problem cannot mix; SMC_E_HIP if capture or instantiation fails. */
 typedef struct {

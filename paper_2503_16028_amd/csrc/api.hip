@@ -1038,7 +1038,8 @@ extern "C" int smc_sampler_graph_create(smc_problem p, const smc_sampler_graph_d
                     d->level ? "the problem's grid count with a level map" : "1 without a level map");
     int64_t off[MAX_LEVELS] = {}, N = 0;
     for (int g = 0; g < G; ++g) {
-        if (d->counts[g] < 1) return fail(SMC_E_INVAL, "counts[%d] must be >= 1", g);
+        if (d->counts[g] < 1 || d->counts[g] > (1 << 20))
+            return fail(SMC_E_INVAL, "counts[%d] must be 1..2^20 (the tempering step's batch)", g);
         off[g] = N;
         N += d->counts[g];
     }

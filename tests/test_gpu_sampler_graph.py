@@ -169,6 +169,14 @@ def test_sampler_graph_rejects_bad_arguments():
         with pytest.raises(smc.SMCError) as e:
             make(**kw)
         assert e.value.status == smc.SMC_E_INVAL, kw
+    B = (1 << 20) + 1                                 # a group beyond the tempering step's batch
+    big = dict(xi=torch.zeros(B, K, **f64), xi2=torch.zeros(B, K, **f64), phi=torch.zeros(B, **f64),
+               phi2=torch.zeros(B, **f64), W=torch.zeros(B, **f64), idx=torch.zeros(B, dtype=torch.int32, device=dev),
+               n_acc=torch.zeros(B, dtype=torch.int32, device=dev))
+    with pytest.raises(smc.SMCError) as e:
+        make(counts=(B,), **big)
+    assert e.value.status == smc.SMC_E_INVAL
+    del big
     g = make()                                       # the stream still captures a valid stage
     g.close()
     s.synchronize()
